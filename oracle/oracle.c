@@ -1,0 +1,230 @@
+/*
+ * CPU ORACLE FOR BREADTH-FIRST SEARCH -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * use this file.  It shares no code with the GPU library: it builds its own
+ * adjacency from the raw edge list and runs a plain serial FIFO search.
+ *
+ * What it computes (paper, Section 2.1, "Breadth-First Search"):
+ *   a parent array from a source with parent[source] = source,
+ *   parent[v] = -1 for unreachable v, and for reachable v with parent u an
+ *   edge u-v and depth[v] = depth[u] + 1.  Depth = hop distance from the
+ *   source, -1 when unreachable.
+ * How it is checked (paper, Section 3, BFS verifier): the parent of the
+ * source is the source, every parent is joined to its child by an edge, and
+ * depths from a trivial serial search show each parent one level above its
+ * child.
+ * Graph clean-up (paper, Section 2.3): removing duplicate edges and
+ * self-loops and reordering neighbours are legal; the benchmark graphs here
+ * are undirected, so every raw pair is inserted in both directions.
+ *
+ * Pins (tests): exhaustive small graphs against Floyd-Warshall and boolean
+ * matrix powers, random graphs against scipy's csgraph, closed forms (path,
+ * cycle, star, complete, bipartite, hypercube, tree, grid), invariants and
+ * union-find reachability on large runs.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- adjacency from the raw edge list --------------------------------- */
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/*
+ * Symmetrised, self-loop-free, duplicate-free adjacency.
+ *   offsets: caller-provided int64[n+1]
+ *   adj:     caller-provided int32[2*m] (upper bound, compacted in place)
+ * Returns the number of adjacency entries, or -1 on bad input.
+ * Lists come out sorted ascending.
+ */
+int64_t oracle_build_adjacency(int64_t n, int64_t m, const int32_t *src,
+                               const int32_t *dst, int64_t *offsets,
+                               int32_t *adj) {
+  if (n < 0 || m < 0 || !offsets || (m > 0 && (!src || !dst || !adj)))
+    return -1;
+  for (int64_t v = 0; v <= n; ++v) offsets[v] = 0;
+  /* count both directions of every pair that is not a self-loop */
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= n || v >= n) return -1;
+    if (u == v) continue;
+    offsets[u + 1] += 1;
+    offsets[v + 1] += 1;
+  }
+  for (int64_t v = 0; v < n; ++v) offsets[v + 1] += offsets[v];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!fill) return -1;
+  for (int64_t v = 0; v < n; ++v) fill[v] = offsets[v];
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u == v) continue;
+    adj[fill[u]++] = v;
+    adj[fill[v]++] = u;
+  }
+  free(fill);
+  /* sort each list, drop repeats, and pack the lists to the left */
+  int64_t out = 0;
+  int64_t start = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t end = offsets[v + 1];
+    int64_t len = end - start;
+    if (len > 1) qsort(adj + start, (size_t)len, sizeof(int32_t), cmp_i32);
+    int64_t row_begin = out;
+    for (int64_t i = start; i < end; ++i) {
+      if (i > start && adj[i] == adj[i - 1]) continue;
+      adj[out++] = adj[i];
+    }
+    offsets[v] = row_begin;
+    start = end;
+  }
+  offsets[n] = out;
+  return out;
+}
+
+/* ---- serial FIFO breadth-first search --------------------------------- */
+
+/*
+ * depth/parent: caller-provided int32[n].  Returns the number of vertices
+ * reached (including the source), or -1 on bad input.  The queue holds every
+ * vertex at most once; neighbours are visited in list order, so the parent
+ * of v is its first discoverer.
+ */
+int64_t oracle_bfs(int64_t n, const int64_t *offsets, const int32_t *adj,
+                   int32_t source, int32_t *depth, int32_t *parent) {
+  if (n <= 0 || source < 0 || source >= n || !offsets || !depth || !parent)
+    return -1;
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!queue) return -1;
+  for (int64_t v = 0; v < n; ++v) {
+    depth[v] = -1;
+    parent[v] = -1;
+  }
+  depth[source] = 0;
+  parent[source] = source;
+  int64_t head = 0, tail = 0;
+  queue[tail++] = source;
+  while (head < tail) {
+    int32_t u = queue[head++];
+    for (int64_t i = offsets[u]; i < offsets[u + 1]; ++i) {
+      int32_t v = adj[i];
+      if (depth[v] == -1) {
+        depth[v] = depth[u] + 1;
+        parent[v] = u;
+        queue[tail++] = v;
+      }
+    }
+  }
+  free(queue);
+  return tail;
+}
+
+/* ---- validator --------------------------------------------------------- */
+
+static int has_edge(const int64_t *offsets, const int32_t *adj, int32_t a,
+                    int32_t b) {
+  int64_t lo = offsets[a], hi = offsets[a + 1];
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (adj[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < offsets[a + 1] && adj[lo] == b;
+}
+
+/*
+ * Checks a result against the definition, using reference depths from
+ * oracle_bfs:
+ *   1  depth_test differs from depth_ref (skipped when depth_test is NULL)
+ *   2  parent[source] != source
+ *   3  reachability of parent disagrees with the reference, or a negative
+ *      value other than -1 appears
+ *   4  parent of a reached vertex is out of range or not a neighbour
+ *   5  parent of a reached vertex is not exactly one level above it
+ * Returns 0 when every check passes; otherwise the first failing check, with
+ * the offending vertex in *bad.
+ */
+int oracle_check(int64_t n, const int64_t *offsets, const int32_t *adj,
+                 int32_t source, const int32_t *depth_ref,
+                 const int32_t *parent, const int32_t *depth_test,
+                 int64_t *bad) {
+  int64_t dummy;
+  if (!bad) bad = &dummy;
+  *bad = -1;
+  if (n <= 0 || source < 0 || source >= n || !parent || !depth_ref) return -1;
+  if (depth_test) {
+    for (int64_t v = 0; v < n; ++v)
+      if (depth_test[v] != depth_ref[v]) {
+        *bad = v;
+        return 1;
+      }
+  }
+  if (parent[source] != source) {
+    *bad = source;
+    return 2;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    if (v == source) continue;
+    int32_t p = parent[v];
+    int reached = depth_ref[v] >= 0;
+    if (!reached) {
+      if (p != -1) {
+        *bad = v;
+        return 3;
+      }
+      continue;
+    }
+    if (p < 0) {
+      *bad = v;
+      return 3;
+    }
+    if (p >= n || !has_edge(offsets, adj, p, (int32_t)v)) {
+      *bad = v;
+      return 4;
+    }
+    if (depth_ref[p] != depth_ref[v] - 1) {
+      *bad = v;
+      return 5;
+    }
+  }
+  return 0;
+}
+
+/* ---- union-find reachability (an independent algorithm) --------------- */
+
+static int32_t uf_find(int32_t *up, int32_t x) {
+  while (up[x] != x) {
+    up[x] = up[up[x]];
+    x = up[x];
+  }
+  return x;
+}
+
+/*
+ * label[v] = a representative of v's connected component, computed from the
+ * raw edge list with union-find (no adjacency, no queue).  Returns 0, or -1
+ * on bad input.
+ */
+int oracle_components(int64_t n, int64_t m, const int32_t *src,
+                      const int32_t *dst, int32_t *label) {
+  if (n <= 0 || m < 0 || !label || (m > 0 && (!src || !dst))) return -1;
+  for (int64_t v = 0; v < n; ++v) label[v] = (int32_t)v;
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t a = src[e], b = dst[e];
+    if (a < 0 || b < 0 || a >= n || b >= n) return -1;
+    int32_t ra = uf_find(label, a), rb = uf_find(label, b);
+    if (ra != rb) {
+      if (ra < rb)
+        label[rb] = ra;
+      else
+        label[ra] = rb;
+    }
+  }
+  for (int64_t v = 0; v < n; ++v) label[v] = uf_find(label, (int32_t)v);
+  return 0;
+}
