@@ -1,0 +1,224 @@
+/*
+ * gapbfs.h -- C ABI of libgapbfs.so: direction-optimizing breadth-first
+ * search on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the BFS kernel of the GAP Benchmark Suite (Beamer,
+ * Asanovic, Patterson, arXiv 1508.03619):
+ *   - Section 2.1, "Breadth-First Search": from a source vertex, produce a
+ *     parent array with parent[source] = source, parent[v] = -1 when v is
+ *     unreachable, and, for every reachable v with parent u, an edge u-v and
+ *     depth[v] = depth[u] + 1.  Several parent arrays are correct; depth (hop
+ *     distance, -1 when unreachable) is unique.
+ *   - Section 2.3: 32-bit vertex identifiers, more than 2^32 edges supported
+ *     (64-bit offsets); duplicate edges and self-loops may be removed and
+ *     neighbours reordered; graph building is untimed, every per-trial
+ *     structure other than the graph is rebuilt per trial.
+ *   - Section 3, BFS: the direction-optimizing search (top-down steps over a
+ *     vertex list, bottom-up steps once the frontier is large), with each
+ *     unvisited vertex's degree stored as a negative number in the parent
+ *     array so the frontier's edge count accrues during top-down steps, and a
+ *     final pass that turns every remaining negative value into -1.
+ *
+ * Conventions for every call:
+ *   - Calls return a gap_status and never abort or throw; gap_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - "device" pointers are HIP device memory on the graph's device (for
+ *     instance the data pointers of torch.cuda tensors); "host" pointers are
+ *     ordinary process memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the legacy
+ *     default stream.  Work is queued on it; outputs are complete once the
+ *     caller synchronises that stream.
+ *   - Vertex IDs are int32 in [0, n); n <= 2^31 - 1.  Offsets and edge
+ *     counts are int64.
+ */
+#ifndef GAPBFS_H
+#define GAPBFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gap_status;
+#define GAP_OK 0
+#define GAP_EINVAL (-1)    /* bad argument (NULL pointer, ID out of range) */
+#define GAP_ENOMEM (-2)    /* device or host allocation failed */
+#define GAP_EDEVICE (-3)   /* no HIP device, or a HIP runtime error */
+#define GAP_EINTERNAL (-5) /* the device reported an inconsistent state */
+#define GAP_ETIMEOUT (-6)  /* a bounded device-side wait gave up */
+
+/* Opaque, immutable graph resident in device memory (CSR). */
+typedef struct gap_graph gap_graph;
+
+/*
+ * gap_build_csr -- build the undirected graph used by every search
+ * (Section 2.3: the graph is loaded and built once, untimed).
+ *   num_vertices  n, 1 <= n <= 2^31 - 1
+ *   num_edges     number of raw pairs, >= 0
+ *   src, dst      host int32[num_edges], each value in [0, n); copied, the
+ *                 caller keeps ownership and may free them on return
+ *   flags         0 (reserved)
+ *   stream        stream used for the upload and build kernels
+ *   out           receives the handle; release it with gap_free
+ * Every pair is inserted in both directions, self-loops and duplicates are
+ * removed, and each neighbour list is sorted ascending.  The result is an
+ * int64 row_ptr[n+1] and an int32 col[nnz] in device memory owned by the
+ * handle.  The call returns after the build has finished.
+ * Errors: GAP_EINVAL (NULL out, n out of range, an ID out of range,
+ * nnz >= 2^32 per call), GAP_ENOMEM, GAP_EDEVICE.
+ */
+gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges,
+                         const int32_t *src, const int32_t *dst,
+                         uint32_t flags, void *stream, gap_graph **out);
+
+/* Vertex count n and stored (directed) adjacency entries nnz = 2|E|. */
+gap_status gap_graph_info(const gap_graph *g, int64_t *n, int64_t *nnz);
+
+/*
+ * gap_graph_export -- copy the CSR to host memory (for cross-checks and
+ * edge counting; not on the search path).  row_ptr: host int64[n+1];
+ * col: host int32[nnz] (either may be NULL to skip it).  Synchronous.
+ */
+gap_status gap_graph_export(const gap_graph *g, int64_t *row_ptr,
+                            int32_t *col);
+
+/*
+ * gap_bfs -- one direction-optimizing search (Section 2.1 output,
+ * Section 3 method).
+ *   g        graph from gap_build_csr
+ *   source   vertex in [0, n); a degree-0 source is legal and reaches only
+ *            itself
+ *   parent   device int32[n], written: parent[source] = source, -1 for
+ *            unreachable vertices, otherwise a neighbour one level closer
+ *   depth    device int32[n] or NULL; written: hop distance, -1 when
+ *            unreachable
+ *   stream   queue for the work
+ * Per-search scratch (queues, bitmaps, counters) comes from a pool the
+ * library keeps per (device, stream); concurrent calls on different
+ * streams are allowed, including on one graph.  With the default
+ * (persistent-kernel) schedule the call only queues work; with the
+ * host-driven schedule it waits on the stream between levels.
+ * Errors: GAP_EINVAL (NULL g or parent, source out of range),
+ * GAP_ENOMEM, GAP_EDEVICE, GAP_ETIMEOUT (reported by the next call on the
+ * stream or by gap_bfs_ex with stats).
+ */
+gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent,
+                   int32_t *depth, void *stream);
+
+/*
+ * gap_bfs_batch -- many searches in one multi-source launch.  Lane i
+ * searches graph graphs[graph_of_source[i]] from sources[i]; each lane's
+ * result is exactly what gap_bfs returns for that (graph, source) (same
+ * depths; parents valid by the same definition).  Lanes of one graph share
+ * 64-bit per-vertex visit/frontier words, so one traversal of the graph
+ * serves up to 64 lanes per word.
+ *   graphs            host array of num_graphs handles (all on one device)
+ *   graph_of_source   host int32[num_sources], values in [0, num_graphs)
+ *   sources           host int32[num_sources], each in [0, n of its graph);
+ *                     repeats are allowed
+ *   parents, depths   host arrays of num_sources device pointers; lane i
+ *                     writes int32[n of its graph] at parents[i] and, when
+ *                     depths is not NULL and depths[i] is not NULL, at
+ *                     depths[i]
+ *   stream            queue for the work
+ * Errors: GAP_EINVAL (NULL arrays, counts <= 0, index or source out of
+ * range, graphs on different devices), GAP_ENOMEM, GAP_EDEVICE.
+ */
+gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
+                         const int32_t *graph_of_source,
+                         const int32_t *sources, int32_t num_sources,
+                         int32_t *const *parents, int32_t *const *depths,
+                         void *stream);
+
+/* Releases the graph (NULL-safe).  Waits for the device to finish any work
+ * queued on it before freeing. */
+void gap_free(gap_graph *g);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char *gap_last_error(void);
+
+/* ---- schedule and tuning ------------------------------------------------
+ * Tuning parameters are properties of the hardware, identical for every
+ * graph (Section 2.3: one implementation and one parameter set for all
+ * input graphs).  They never change results: depths are unique and every
+ * schedule returns valid parents.
+ */
+#define GAP_MODE_PERSISTENT 0 /* one cooperative kernel, grid barriers */
+#define GAP_MODE_LEVELS 1     /* one launch per step, host reads counters */
+#define GAP_MODE_GRAPH 2      /* hipGraph chunks of levels, device-decided */
+
+#define GAP_DIR_AUTO 0    /* edge/vertex-count switching heuristic */
+#define GAP_DIR_TOPDOWN 1 /* top-down steps only */
+#define GAP_DIR_BOTTOMUP 2 /* bottom-up from the first level on */
+
+typedef struct gap_params {
+  int32_t mode;          /* GAP_MODE_* */
+  int32_t direction;     /* GAP_DIR_* */
+  int32_t alpha;         /* top-down -> bottom-up when m_f > m_u / alpha */
+  int32_t beta;          /* bottom-up -> top-down when n_f < n / beta and
+                            the frontier shrank */
+  int32_t block;         /* threads per workgroup: 256, 512 or 1024 */
+  int32_t blocks_per_cu; /* persistent grid: workgroups per compute unit
+                            (0 = as many as fit) */
+  int32_t hub_degree;    /* top-down: vertices of larger degree are split
+                            into chunk work items */
+  int32_t chunk_edges;   /* edges per chunk work item (multiple of 64) */
+  int32_t graph_chunk;   /* GAP_MODE_GRAPH: levels per captured graph */
+  int32_t batch_mode;    /* multi-source: 0 persistent, 1 per-level */
+  int32_t reserved[6];
+} gap_params;
+
+/* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */
+gap_status gap_set_params(const gap_params *p);
+gap_status gap_get_params(gap_params *p);
+
+/* Per-level record of one search, for measurement and tests. */
+typedef struct gap_level_stat {
+  int32_t level;        /* depth d of the frontier expanded at this step */
+  int32_t direction;    /* 1 top-down, 2 bottom-up */
+  int64_t frontier;     /* |F_d| */
+  int64_t frontier_edges; /* sum of degrees over F_d */
+  int64_t claimed;      /* |F_{d+1}| */
+  int64_t scanned;      /* adjacency entries read by the step */
+  int64_t unvisited;    /* bottom-up: vertices still searching a parent */
+} gap_level_stat;
+
+/*
+ * gap_bfs_ex -- gap_bfs with an explicit parameter set (NULL = process-wide)
+ * and, when `stats` is not NULL, per-level records (synchronous: waits for
+ * the search, then copies at most max_levels records and writes the level
+ * count to *num_levels).  Counting adds device atomics; timed runs pass NULL.
+ */
+gap_status gap_bfs_ex(const gap_graph *g, int32_t source, int32_t *parent,
+                      int32_t *depth, void *stream, const gap_params *params,
+                      gap_level_stat *stats, int32_t max_levels,
+                      int32_t *num_levels);
+
+/* Device facts used by the tuner and the benchmark. */
+typedef struct gap_device_info {
+  int32_t device;
+  int32_t compute_units;
+  int32_t lds_per_cu;      /* bytes */
+  int32_t l2_bytes;
+  int32_t wave_size;
+  int32_t clock_khz;
+  int64_t total_mem;
+  char arch[64];
+} gap_device_info;
+
+gap_status gap_device_query(gap_device_info *info);
+
+/*
+ * gap_stream_copy -- HBM bandwidth probe: copies `bytes` (multiple of 16)
+ * from src to dst (device pointers, non-overlapping) with the library's
+ * streaming-copy kernel on `stream`.
+ */
+gap_status gap_stream_copy(void *dst, const void *src, int64_t bytes,
+                           void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAPBFS_H */

@@ -1,0 +1,424 @@
+// C ABI of libgapbfs and its host runtime: errors, device facts, per-stream
+// workspaces, the parameter set.
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "runtime.h"
+
+namespace gap {
+
+static thread_local std::string t_error;
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  t_error = buf;
+}
+
+void clear_error() { t_error.clear(); }
+
+gap_status hip_fail(hipError_t e, const char *what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return GAP_ENOMEM;
+  return GAP_EDEVICE;
+}
+
+// ---- device facts ---------------------------------------------------------------
+
+static std::mutex g_mu;
+static std::map<int, DeviceInfo> g_dev;
+
+gap_status device_info(int dev, const DeviceInfo **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) {
+    hipDeviceProp_t prop;
+    GAP_HIP(hipGetDeviceProperties(&prop, dev));
+    DeviceInfo di;
+    di.device = dev;
+    di.cus = prop.multiProcessorCount;
+    di.lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    di.l2_bytes = prop.l2CacheSize;
+    di.clock_khz = prop.clockRate;
+    di.total_mem = prop.totalGlobalMem;
+    di.coop_supported = prop.cooperativeLaunch;
+    snprintf(di.arch, sizeof(di.arch), "%s", prop.gcnArchName);
+    it = g_dev.emplace(dev, di).first;
+  }
+  *out = &it->second;
+  return GAP_OK;
+}
+
+// ---- parameters --------------------------------------------------------------------
+
+static gap_params default_params() {
+  gap_params p;
+  memset(&p, 0, sizeof(p));
+  p.mode = GAP_MODE_PERSISTENT;
+  p.direction = GAP_DIR_AUTO;
+  p.alpha = 15;
+  p.beta = 18;
+  p.block = 256;
+  p.blocks_per_cu = 0;
+  p.hub_degree = 256;
+  p.chunk_edges = 256;
+  p.graph_chunk = 16;
+  p.batch_mode = 0;
+  return p;
+}
+
+static gap_params g_params = default_params();
+
+gap_params params_current() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_params;
+}
+
+gap_status params_check(const gap_params &p) {
+  if (p.mode < GAP_MODE_PERSISTENT || p.mode > GAP_MODE_GRAPH) {
+    set_error("params: mode %d out of range", p.mode);
+    return GAP_EINVAL;
+  }
+  if (p.direction < GAP_DIR_AUTO || p.direction > GAP_DIR_BOTTOMUP) {
+    set_error("params: direction %d out of range", p.direction);
+    return GAP_EINVAL;
+  }
+  if (p.alpha < 1 || p.beta < 1) {
+    set_error("params: alpha and beta must be >= 1");
+    return GAP_EINVAL;
+  }
+  if (p.block != 256 && p.block != 512 && p.block != 1024) {
+    set_error("params: block must be 256, 512 or 1024");
+    return GAP_EINVAL;
+  }
+  if (p.blocks_per_cu < 0 || p.blocks_per_cu > 32) {
+    set_error("params: blocks_per_cu must be in [0, 32]");
+    return GAP_EINVAL;
+  }
+  if (p.hub_degree < 1 || p.hub_degree > (1 << 20)) {
+    set_error("params: hub_degree must be in [1, 2^20]");
+    return GAP_EINVAL;
+  }
+  if (p.chunk_edges < 64 || p.chunk_edges > (1 << 20) || p.chunk_edges % 64 != 0) {
+    set_error("params: chunk_edges must be a multiple of 64 in [64, 2^20]");
+    return GAP_EINVAL;
+  }
+  if (p.graph_chunk < 1 || p.graph_chunk > 4096) {
+    set_error("params: graph_chunk must be in [1, 4096]");
+    return GAP_EINVAL;
+  }
+  if (p.batch_mode < 0 || p.batch_mode > 1) {
+    set_error("params: batch_mode must be 0 or 1");
+    return GAP_EINVAL;
+  }
+  return GAP_OK;
+}
+
+// ---- workspaces ---------------------------------------------------------------------
+
+static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace *workspace_for(int dev, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, stream);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) return it->second.get();
+  std::unique_ptr<Workspace> ws(new (std::nothrow) Workspace());
+  if (!ws) return nullptr;
+  ws->device = dev;
+  ws->stream = stream;
+  Workspace *raw = ws.get();
+  g_ws.emplace(key, std::move(ws));
+  return raw;
+}
+
+template <class T>
+static void free_dev(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+static void release_single(Workspace *ws) {
+  for (auto &q : ws->q) free_dev(q);
+  for (auto &c : ws->cq) free_dev(c);
+  for (auto &b : ws->bm) free_dev(b);
+  free_dev(ws->depth_scratch);
+  free_dev(ws->ctl);
+  if (ws->h_cnt) (void)hipHostFree(ws->h_cnt);
+  ws->h_cnt = nullptr;
+  ws->cap_n = 0;
+  ws->cap_chunks = 0;
+}
+
+gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const gap_params &p) {
+  // Each vertex enters a queue at most once per search, so n slots suffice;
+  // hub chunk items are bounded by nnz/chunk + nnz/hub (one partial chunk per
+  // vertex of degree > hub, and there are at most nnz/hub of those).
+  const int64_t chunks = nnz / p.chunk_edges + nnz / p.hub_degree + 2;
+  if (ws->cap_n >= n && ws->cap_chunks >= chunks && ws->ctl) return GAP_OK;
+  if (ws->ctl) GAP_HIP(hipStreamSynchronize(ws->stream));
+  const int64_t cap_n = std::max<int64_t>(n, ws->cap_n);
+  const int64_t cap_c = std::max<int64_t>(chunks, ws->cap_chunks);
+  release_single(ws);
+  const int64_t words = (cap_n + 63) / 64 + 1;
+  hipError_t e = hipSuccess;
+  for (auto &q : ws->q)
+    if (e == hipSuccess) e = hipMalloc(&q, sizeof(int32_t) * (size_t)cap_n);
+  for (auto &c : ws->cq)
+    if (e == hipSuccess) e = hipMalloc(&c, sizeof(int2) * (size_t)cap_c);
+  for (auto &b : ws->bm)
+    if (e == hipSuccess) e = hipMalloc(&b, sizeof(uint64_t) * (size_t)words);
+  if (e == hipSuccess) e = hipMalloc(&ws->depth_scratch, sizeof(int32_t) * (size_t)cap_n);
+  if (e == hipSuccess) e = hipMalloc(&ws->ctl, sizeof(Ctl));
+  if (e == hipSuccess) e = hipHostMalloc(&ws->h_cnt, sizeof(LevelCounters));
+  if (e == hipSuccess) e = hipMemset(ws->ctl, 0, sizeof(Ctl));
+  if (e != hipSuccess) {
+    release_single(ws);
+    return hip_fail(e, "workspace allocation");
+  }
+  ws->cap_n = cap_n;
+  ws->cap_chunks = cap_c;
+  return GAP_OK;
+}
+
+gap_status workspace_reserve_recs(Workspace *ws, int32_t nrec) {
+  if (ws->cap_recs >= nrec) return GAP_OK;
+  GAP_HIP(hipStreamSynchronize(ws->stream));
+  free_dev(ws->recs);
+  ws->cap_recs = 0;
+  GAP_HIP(hipMalloc(&ws->recs, sizeof(DevLevelRec) * (size_t)nrec));
+  ws->cap_recs = nrec;
+  return GAP_OK;
+}
+
+gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes) {
+  if (ws->ms_bytes < bytes) {
+    GAP_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->ms_buf) (void)hipFree(ws->ms_buf);
+    ws->ms_buf = nullptr;
+    ws->ms_bytes = 0;
+    GAP_HIP(hipMalloc(&ws->ms_buf, bytes));
+    ws->ms_bytes = bytes;
+  }
+  if (ws->ms_host_bytes < host_bytes) {
+    GAP_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->ms_host) (void)hipHostFree(ws->ms_host);
+    ws->ms_host = nullptr;
+    ws->ms_host_bytes = 0;
+    GAP_HIP(hipHostMalloc(&ws->ms_host, host_bytes));
+    ws->ms_host_bytes = host_bytes;
+  }
+  return GAP_OK;
+}
+
+}  // namespace gap
+
+using namespace gap;
+
+// ---- C ABI --------------------------------------------------------------------------
+
+extern "C" {
+
+const char *gap_last_error(void) { return t_error.c_str(); }
+
+gap_status gap_device_query(gap_device_info *info) {
+  if (!info) {
+    set_error("gap_device_query: NULL info");
+    return GAP_EINVAL;
+  }
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) {
+    set_error("no HIP device available");
+    return GAP_EDEVICE;
+  }
+  int dev = 0;
+  GAP_HIP(hipGetDevice(&dev));
+  const DeviceInfo *di = nullptr;
+  gap_status st = device_info(dev, &di);
+  if (st != GAP_OK) return st;
+  memset(info, 0, sizeof(*info));
+  info->device = dev;
+  info->compute_units = di->cus;
+  info->lds_per_cu = di->lds_per_cu;
+  info->l2_bytes = di->l2_bytes;
+  info->wave_size = kWave;
+  info->clock_khz = di->clock_khz;
+  info->total_mem = (int64_t)di->total_mem;
+  snprintf(info->arch, sizeof(info->arch), "%s", di->arch);
+  return GAP_OK;
+}
+
+gap_status gap_set_params(const gap_params *p) {
+  if (!p) {
+    set_error("gap_set_params: NULL");
+    return GAP_EINVAL;
+  }
+  gap_status st = params_check(*p);
+  if (st != GAP_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_params = *p;
+  return GAP_OK;
+}
+
+gap_status gap_get_params(gap_params *p) {
+  if (!p) {
+    set_error("gap_get_params: NULL");
+    return GAP_EINVAL;
+  }
+  *p = params_current();
+  return GAP_OK;
+}
+
+static gap_status require_device() {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) {
+    set_error("no HIP device available");
+    return GAP_EDEVICE;
+  }
+  return GAP_OK;
+}
+
+gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges, const int32_t *src,
+                         const int32_t *dst, uint32_t flags, void *stream, gap_graph **out) {
+  clear_error();
+  if (!out) {
+    set_error("gap_build_csr: NULL out");
+    return GAP_EINVAL;
+  }
+  *out = nullptr;
+  if (num_vertices < 1 || num_vertices > 2147483647ll) {
+    set_error("gap_build_csr: n = %lld outside [1, 2^31-1]", (long long)num_vertices);
+    return GAP_EINVAL;
+  }
+  if (num_edges < 0 || (num_edges > 0 && (!src || !dst))) {
+    set_error("gap_build_csr: bad edge arrays");
+    return GAP_EINVAL;
+  }
+  if (flags != 0) {
+    set_error("gap_build_csr: flags must be 0");
+    return GAP_EINVAL;
+  }
+  gap_status st = require_device();
+  if (st != GAP_OK) return st;
+  return build_csr(num_vertices, num_edges, src, dst, (hipStream_t)stream, out);
+}
+
+gap_status gap_graph_info(const gap_graph *g, int64_t *n, int64_t *nnz) {
+  if (!g) {
+    set_error("gap_graph_info: NULL graph");
+    return GAP_EINVAL;
+  }
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  return GAP_OK;
+}
+
+gap_status gap_graph_export(const gap_graph *g, int64_t *row_ptr, int32_t *col) {
+  if (!g) {
+    set_error("gap_graph_export: NULL graph");
+    return GAP_EINVAL;
+  }
+  GAP_HIP(hipSetDevice(g->device));
+  if (row_ptr)
+    GAP_HIP(hipMemcpy(row_ptr, g->row_ptr, sizeof(int64_t) * (size_t)(g->n + 1),
+                      hipMemcpyDeviceToHost));
+  if (col && g->nnz > 0)
+    GAP_HIP(hipMemcpy(col, g->col, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost));
+  return GAP_OK;
+}
+
+gap_status gap_bfs_ex(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
+                      void *stream, const gap_params *params, gap_level_stat *stats,
+                      int32_t max_levels, int32_t *num_levels) {
+  clear_error();
+  if (!g || !parent) {
+    set_error("gap_bfs: NULL %s", g ? "parent" : "graph");
+    return GAP_EINVAL;
+  }
+  if (source < 0 || (int64_t)source >= g->n) {
+    set_error("gap_bfs: source %d outside [0, %lld)", source, (long long)g->n);
+    return GAP_EINVAL;
+  }
+  gap_params p = params ? *params : params_current();
+  if (params) {
+    gap_status st = params_check(p);
+    if (st != GAP_OK) return st;
+  }
+  return run_bfs(g, source, parent, depth, (hipStream_t)stream, p, stats, max_levels, num_levels);
+}
+
+gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
+                   void *stream) {
+  return gap_bfs_ex(g, source, parent, depth, stream, nullptr, nullptr, 0, nullptr);
+}
+
+gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
+                         const int32_t *graph_of_source, const int32_t *sources,
+                         int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
+                         void *stream) {
+  clear_error();
+  if (!graphs || !graph_of_source || !sources || !parents) {
+    set_error("gap_bfs_batch: NULL array");
+    return GAP_EINVAL;
+  }
+  if (num_graphs <= 0 || num_sources <= 0) {
+    set_error("gap_bfs_batch: counts must be positive");
+    return GAP_EINVAL;
+  }
+  for (int32_t i = 0; i < num_graphs; ++i) {
+    if (!graphs[i]) {
+      set_error("gap_bfs_batch: graph %d is NULL", i);
+      return GAP_EINVAL;
+    }
+    if (graphs[i]->device != graphs[0]->device) {
+      set_error("gap_bfs_batch: graphs on different devices");
+      return GAP_EINVAL;
+    }
+  }
+  for (int32_t i = 0; i < num_sources; ++i) {
+    const int32_t gi = graph_of_source[i];
+    if (gi < 0 || gi >= num_graphs) {
+      set_error("gap_bfs_batch: graph_of_source[%d] = %d out of range", i, gi);
+      return GAP_EINVAL;
+    }
+    if (sources[i] < 0 || (int64_t)sources[i] >= graphs[gi]->n) {
+      set_error("gap_bfs_batch: sources[%d] = %d out of range", i, sources[i]);
+      return GAP_EINVAL;
+    }
+    if (!parents[i]) {
+      set_error("gap_bfs_batch: parents[%d] is NULL", i);
+      return GAP_EINVAL;
+    }
+  }
+  return run_bfs_batch(graphs, num_graphs, graph_of_source, sources, num_sources, parents, depths,
+                       (hipStream_t)stream, params_current());
+}
+
+void gap_free(gap_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  if (g->row_ptr) (void)hipFree(g->row_ptr);
+  if (g->col) (void)hipFree(g->col);
+  delete g;
+}
+
+gap_status gap_stream_copy(void *dst, const void *src, int64_t bytes, void *stream) {
+  clear_error();
+  if (!dst || !src || bytes < 0 || bytes % 16 != 0) {
+    set_error("gap_stream_copy: bad arguments");
+    return GAP_EINVAL;
+  }
+  return stream_copy(dst, src, bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

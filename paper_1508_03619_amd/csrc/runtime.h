@@ -1,0 +1,101 @@
+// Host runtime of libgapbfs: graph handle, device facts, per-stream
+// workspaces and the parameter set.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+struct gap_graph {
+  int device;
+  int64_t n;
+  int64_t nnz;
+  int64_t *row_ptr;  // device int64[n+1]
+  int32_t *col;      // device int32[nnz]
+  int64_t max_degree;
+};
+
+namespace gap {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+// Maps a HIP error to a status and records a message.
+gap_status hip_fail(hipError_t e, const char *what);
+#define GAP_HIP(call)                                   \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return ::gap::hip_fail(_e, #call); \
+  } while (0)
+
+struct DeviceInfo {
+  int device = -1;
+  int cus = 0;
+  int lds_per_cu = 0;
+  int l2_bytes = 0;
+  int clock_khz = 0;
+  size_t total_mem = 0;
+  char arch[64] = {0};
+  int coop_supported = 0;
+};
+
+gap_status device_info(int dev, const DeviceInfo **out);
+
+// Per-level record kept on the device when statistics are requested.
+struct DevLevelRec {
+  int32_t level, direction;
+  unsigned long long frontier, frontier_edges, claimed, scanned, unvisited;
+};
+
+// Scratch for searches queued on one (device, stream).  Reused by calls in
+// stream order; grown (after a stream synchronisation) when a larger graph
+// or a smaller hub/chunk setting needs more room.
+struct Workspace {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  // single source
+  int64_t cap_n = 0;
+  int64_t cap_chunks = 0;
+  int32_t *q[2] = {nullptr, nullptr};
+  int2 *cq[2] = {nullptr, nullptr};
+  uint64_t *bm[3] = {nullptr, nullptr, nullptr};  // frontier A, frontier B, visited
+  int32_t *depth_scratch = nullptr;
+  Ctl *ctl = nullptr;
+  LevelCounters *h_cnt = nullptr;  // pinned readback
+  DevLevelRec *recs = nullptr;
+  int32_t cap_recs = 0;
+  // multi-source
+  size_t ms_bytes = 0;
+  void *ms_buf = nullptr;
+  size_t ms_host_bytes = 0;
+  void *ms_host = nullptr;  // pinned staging for per-lane metadata
+};
+
+Workspace *workspace_for(int dev, hipStream_t stream);
+gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const gap_params &p);
+gap_status workspace_reserve_recs(Workspace *ws, int32_t nrec);
+gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes);
+
+gap_params params_current();
+gap_status params_check(const gap_params &p);
+
+// Implemented in bfs.hip
+gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
+                   hipStream_t stream, const gap_params &p, gap_level_stat *stats,
+                   int32_t max_levels, int32_t *num_levels);
+// Implemented in msbfs.hip
+gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
+                         const int32_t *graph_of_source, const int32_t *sources,
+                         int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
+                         hipStream_t stream, const gap_params &p);
+// Implemented in build_csr.hip
+gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     hipStream_t stream, gap_graph **out);
+gap_status stream_copy(void *dst, const void *src, int64_t bytes, hipStream_t stream);
+
+}  // namespace gap

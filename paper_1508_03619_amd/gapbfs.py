@@ -1,0 +1,274 @@
+"""ctypes binding of libgapbfs.so (include/gapbfs.h).
+
+Argument marshalling only: every step of the search runs in the library's
+HIP kernels.  Device buffers are torch tensors (int32, on the graph's
+device); streams are torch streams (their ``cuda_stream`` handle).  If the
+library is not built, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgapbfs.so")
+_lib = None
+_lock = threading.Lock()
+
+GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_EDEVICE, GAP_EINTERNAL, GAP_ETIMEOUT = 0, -1, -2, -3, -5, -6
+MODE_PERSISTENT, MODE_LEVELS, MODE_GRAPH = 0, 1, 2
+DIR_AUTO, DIR_TOPDOWN, DIR_BOTTOMUP = 0, 1, 2
+
+
+class GapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gapbfs status {status}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("direction", ctypes.c_int32),
+                ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("hub_degree", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
+                ("graph_chunk", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+PARAM_NAMES = [f[0] for f in _Params._fields_ if f[0] != "reserved"]
+
+
+class LevelStat(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("direction", ctypes.c_int32),
+                ("frontier", ctypes.c_int64), ("frontier_edges", ctypes.c_int64),
+                ("claimed", ctypes.c_int64), ("scanned", ctypes.c_int64),
+                ("unvisited", ctypes.c_int64)]
+
+
+class DeviceInfo(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("compute_units", ctypes.c_int32),
+                ("lds_per_cu", ctypes.c_int32), ("l2_bytes", ctypes.c_int32),
+                ("wave_size", ctypes.c_int32), ("clock_khz", ctypes.c_int32),
+                ("total_mem", ctypes.c_int64), ("arch", ctypes.c_char * 64)]
+
+
+EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_bfs", "gap_bfs_batch",
+            "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
+            "gap_device_query", "gap_stream_copy"]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libgapbfs.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is not built (run __graft_entry__.build() or "
+                              "python -m paper_1508_03619_amd.build)")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.gap_build_csr.argtypes = [i64, i64, i32p, i32p, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+        L.gap_graph_info.argtypes = [vp, i64p, i64p]
+        L.gap_graph_export.argtypes = [vp, i64p, i32p]
+        L.gap_bfs.argtypes = [vp, i32, vp, vp, vp]
+        L.gap_bfs_ex.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(_Params),
+                                 ctypes.POINTER(LevelStat), i32, i32p]
+        L.gap_bfs_batch.argtypes = [ctypes.POINTER(vp), i32, i32p, i32p, i32,
+                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.gap_free.argtypes = [vp]
+        L.gap_free.restype = None
+        L.gap_last_error.argtypes = []
+        L.gap_last_error.restype = ctypes.c_char_p
+        L.gap_set_params.argtypes = [ctypes.POINTER(_Params)]
+        L.gap_get_params.argtypes = [ctypes.POINTER(_Params)]
+        L.gap_device_query.argtypes = [ctypes.POINTER(DeviceInfo)]
+        L.gap_stream_copy.argtypes = [vp, vp, i64, vp]
+        for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_bfs", "gap_bfs_ex",
+                     "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
+                     "gap_stream_copy"):
+            getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+        return L
+
+
+def _check(status: int):
+    if status != GAP_OK:
+        msg = load().gap_last_error()
+        raise GapError(status, msg.decode() if msg else "")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _i32p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Graph:
+    """A CSR graph resident in device memory (owns its gap_graph handle)."""
+
+    def __init__(self, handle: int, n: int, nnz: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.n = n
+        self.nnz = nnz
+
+    def free(self):
+        if self.handle and self.handle.value:
+            load().gap_free(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self):
+        """(row_ptr int64[n+1], col int32[nnz]) copied to the host."""
+        row_ptr = np.empty(self.n + 1, np.int64)
+        col = np.empty(max(self.nnz, 1), np.int32)
+        _check(load().gap_graph_export(self.handle, row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       _i32p(col)))
+        return row_ptr, col[:self.nnz]
+
+    def degrees(self) -> np.ndarray:
+        rp, _ = self.export_row_ptr()
+        return np.diff(rp)
+
+    def export_row_ptr(self):
+        row_ptr = np.empty(self.n + 1, np.int64)
+        _check(load().gap_graph_export(self.handle, row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       None))
+        return row_ptr, None
+
+
+def build_csr(n: int, src: np.ndarray, dst: np.ndarray, stream=None) -> Graph:
+    L = load()
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(L.gap_build_csr(int(n), int(src.shape[0]), _i32p(src), _i32p(dst), 0,
+                           _stream_handle(stream), ctypes.byref(out)))
+    nn, nnz = ctypes.c_int64(), ctypes.c_int64()
+    _check(L.gap_graph_info(out, ctypes.byref(nn), ctypes.byref(nnz)))
+    return Graph(out.value, nn.value, nnz.value)
+
+
+def graph_info(g: Graph):
+    return g.n, g.nnz
+
+
+def free(g: Graph):
+    g.free()
+
+
+def _params_struct(d: dict) -> _Params:
+    p = _Params()
+    _check(load().gap_get_params(ctypes.byref(p)))
+    for k, v in d.items():
+        if k not in PARAM_NAMES:
+            raise KeyError(k)
+        setattr(p, k, int(v))
+    return p
+
+
+def get_params() -> dict:
+    p = _Params()
+    _check(load().gap_get_params(ctypes.byref(p)))
+    return {k: int(getattr(p, k)) for k in PARAM_NAMES}
+
+
+def set_params(**kw):
+    p = _params_struct(kw)
+    _check(load().gap_set_params(ctypes.byref(p)))
+
+
+_last_stats: list = []
+
+
+def last_stats() -> list:
+    return list(_last_stats)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("output buffers must be contiguous int32 device tensors")
+    return t.data_ptr()
+
+
+def bfs(g: Graph, source: int, parent, depth=None, stream=None, params: Optional[dict] = None,
+        stats: bool = False, max_levels: int = 1 << 16):
+    """One search.  parent/depth: int32 device tensors of length n (depth may be None).
+    With stats=True the call waits for the search and returns per-level records."""
+    L = load()
+    if parent.numel() < g.n or (depth is not None and depth.numel() < g.n):
+        raise ValueError("output buffers shorter than n")
+    if params is None and not stats:
+        _check(L.gap_bfs(g.handle, int(source), _ptr(parent), _ptr(depth), _stream_handle(stream)))
+        return None
+    pp = ctypes.byref(_params_struct(params)) if params is not None else None
+    if stats:
+        recs = (LevelStat * max_levels)()
+        nl = ctypes.c_int32(0)
+        _check(L.gap_bfs_ex(g.handle, int(source), _ptr(parent), _ptr(depth), _stream_handle(stream),
+                            pp, recs, int(max_levels), ctypes.byref(nl)))
+        out = [{k: int(getattr(recs[i], k)) for k, _ in LevelStat._fields_}
+               for i in range(min(nl.value, max_levels))]
+        _last_stats[:] = out
+        return out
+    _check(L.gap_bfs_ex(g.handle, int(source), _ptr(parent), _ptr(depth), _stream_handle(stream),
+                        pp, None, 0, None))
+    return None
+
+
+def bfs_batch(graphs: Sequence[Graph], graph_of_source: Sequence[int], sources: Sequence[int],
+              parents: Sequence, depths: Optional[Sequence] = None, stream=None):
+    """Lane i searches graphs[graph_of_source[i]] from sources[i]."""
+    L = load()
+    ng, ns = len(graphs), len(sources)
+    gh = (ctypes.c_void_p * ng)(*[g.handle.value for g in graphs])
+    gos = np.ascontiguousarray(graph_of_source, dtype=np.int32)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    if len(gos) != ns or len(parents) != ns or (depths is not None and len(depths) != ns):
+        raise ValueError("per-lane arrays must all have num_sources entries")
+    for i in range(ns):
+        n = graphs[int(gos[i])].n
+        if parents[i].numel() < n or (depths is not None and depths[i] is not None and depths[i].numel() < n):
+            raise ValueError(f"lane {i}: output buffer shorter than n")
+    pa = (ctypes.c_void_p * ns)(*[_ptr(t) for t in parents])
+    da = None
+    if depths is not None:
+        da = (ctypes.c_void_p * ns)(*[_ptr(t) for t in depths])
+    _check(L.gap_bfs_batch(gh, ng, _i32p(gos), _i32p(src), ns, pa, da, _stream_handle(stream)))
+
+
+def device_query() -> dict:
+    info = DeviceInfo()
+    _check(load().gap_device_query(ctypes.byref(info)))
+    d = {k: getattr(info, k) for k, _ in DeviceInfo._fields_}
+    d["arch"] = info.arch.decode()
+    return d
+
+
+def stream_copy(dst, src, nbytes: int, stream=None):
+    _check(load().gap_stream_copy(dst.data_ptr(), src.data_ptr(), int(nbytes), _stream_handle(stream)))

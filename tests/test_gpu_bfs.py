@@ -1,0 +1,213 @@
+"""Single-source parity on the device: depths bit-exact against the CPU
+oracle, parents valid by the definition (Section 2.1), through the C ABI."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import smallgraphs as sg
+from tests.gpuutil import assert_valid, device_bfs, graph_pair, say
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [
+    dict(mode=0, direction=0), dict(mode=0, direction=1), dict(mode=0, direction=2),
+    dict(mode=1, direction=0), dict(mode=1, direction=1), dict(mode=1, direction=2),
+]
+
+
+def small_cases():
+    cases = [(name, n, s, d) for name, n, s, d, _ in sg.read_golden()]
+    for name, mk in [("path33", lambda: sg.path(33)), ("cycle70", lambda: sg.cycle(70)),
+                     ("star130", lambda: sg.star(130)), ("K12", lambda: sg.complete(12)),
+                     ("K5,70", lambda: sg.bipartite(5, 70)), ("Q7", lambda: sg.hypercube(7)),
+                     ("grid13x11", lambda: sg.full_grid(13, 11)),
+                     ("union", lambda: sg.disjoint_union(sg.path(5), sg.cycle(65), sg.path(1), sg.star(3)))]:
+        n, s, d, _ = mk()
+        cases.append((name, n, s, d))
+    return cases
+
+
+def test_golden_depths_on_device(gpu):
+    for name, n, s, d, cases in sg.read_golden():
+        say(f"golden {name}")
+        g = gpu.build_csr(n, s, d)
+        for src, want in cases:
+            for sch in SCHEDULES:
+                parent, depth = device_bfs(gpu, g, src, params=sch)
+                assert np.array_equal(depth, want), (name, src, sch)
+        g.free()
+
+
+def test_small_graphs_all_sources_all_schedules(gpu):
+    for name, n, s, d in small_cases():
+        say(f"small {name} n={n}")
+        g, A = graph_pair(gpu, n, s, d)
+        for src in range(n):
+            ref = A.bfs(src)[0]
+            for sch in SCHEDULES:
+                parent, depth = device_bfs(gpu, g, src, params=sch)
+                assert_valid(A, src, parent, depth, ref, what=f"{name} {sch}")
+        g.free()
+
+
+def test_random_graphs_with_repeats_and_self_loops(gpu):
+    for seed in range(40):
+        rng = np.random.default_rng(1000 + seed)
+        n = int(rng.integers(1, 300))
+        m = int(rng.integers(0, 4 * n + 1))
+        s = rng.integers(0, n, m).astype(np.int32)
+        d = rng.integers(0, n, m).astype(np.int32)
+        if m:
+            s = np.concatenate([s, s[: m // 5 + 1], d[: m // 7 + 1]]).astype(np.int32)
+            d = np.concatenate([d, d[: m // 5 + 1], d[: m // 7 + 1]]).astype(np.int32)
+        say(f"random seed={seed} n={n} m={len(s)}")
+        g, A = graph_pair(gpu, n, s, d)
+        for src in rng.integers(0, n, 6):
+            ref = A.bfs(int(src))[0]
+            for sch in SCHEDULES:
+                parent, depth = device_bfs(gpu, g, int(src), params=sch)
+                assert_valid(A, int(src), parent, depth, ref, what=f"seed {seed} {sch}")
+        g.free()
+
+
+def test_csr_matches_oracle_adjacency(gpu):
+    from paper_1508_03619_amd import inputs
+    for el in (inputs.rmat(14, 16, seed=3), inputs.grid(40, 30, seed=5),
+               inputs.urand(3000, 40000, seed=9)):
+        say(f"csr {el.name}")
+        g = gpu.build_csr(el.n, el.src, el.dst)
+        A = oracle.Adjacency(el.n, el.src, el.dst)
+        row_ptr, col = g.export()
+        assert np.array_equal(row_ptr, A.offsets)
+        assert np.array_equal(col, A.adj)
+        g.free()
+
+
+def test_edge_cases(gpu):
+    say("edge cases")
+    # one vertex, no edges
+    g, A = graph_pair(gpu, 1, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    for sch in SCHEDULES:
+        parent, depth = device_bfs(gpu, g, 0, params=sch)
+        assert parent.tolist() == [0] and depth.tolist() == [0]
+    # only self-loops
+    g, A = graph_pair(gpu, 70, np.arange(70, dtype=np.int32), np.arange(70, dtype=np.int32))
+    assert g.nnz == 0
+    for sch in SCHEDULES:
+        parent, depth = device_bfs(gpu, g, 69, params=sch)
+        assert_valid(A, 69, parent, depth)
+    # isolated source in a graph with edges, ragged n, source n-1
+    for n in (63, 64, 65, 127, 129):
+        s = np.arange(0, n - 3, dtype=np.int32)
+        d = (s + 1).astype(np.int32)
+        g, A = graph_pair(gpu, n, s, d)
+        for src in (0, n - 3, n - 2, n - 1):
+            for sch in SCHEDULES:
+                parent, depth = device_bfs(gpu, g, src, params=sch)
+                assert_valid(A, src, parent, depth, what=f"n={n} {sch}")
+    # depth output omitted
+    g, A = graph_pair(gpu, 100, np.arange(99, dtype=np.int32), np.arange(1, 100, dtype=np.int32))
+    parent, _ = device_bfs(gpu, g, 50, with_depth=False)
+    dref = A.bfs(50)[0]
+    assert A.check(50, dref, parent)[0] == 0
+
+
+def test_hub_splitting_and_tuning_invariance(gpu):
+    """Every parameter setting gives the same depths (they are unique)."""
+    from paper_1508_03619_amd import inputs
+    el = inputs.rmat(14, 16, seed=21)
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    deg = np.diff(A.offsets)
+    srcs = [int(np.argmax(deg))] + [int(x) for x in inputs.pick_sources(el, 3, seed=22)]
+    settings = [dict(hub_degree=1, chunk_edges=64), dict(hub_degree=64, chunk_edges=64),
+                dict(hub_degree=4096, chunk_edges=1024), dict(alpha=1, beta=1),
+                dict(alpha=1000, beta=1000), dict(alpha=2, beta=200),
+                dict(block=512), dict(block=1024), dict(block=256, blocks_per_cu=1),
+                dict(block=1024, blocks_per_cu=1)]
+    for src in srcs:
+        ref = A.bfs(src)[0]
+        for st in settings:
+            for mode in (0, 1):
+                say(f"tuning src={src} {st} mode={mode}")
+                parent, depth = device_bfs(gpu, g, src, params=dict(st, mode=mode))
+                assert_valid(A, src, parent, depth, ref, what=str(st))
+
+
+def test_rmat16_64_sources(gpu):
+    """R-MAT scale 16, edge factor 16, 64 seeded non-zero-degree sources."""
+    from paper_1508_03619_amd import inputs
+    el = inputs.workload("rmat16")
+    srcs = inputs.pick_sources(el, 64, seed=inputs.SOURCE_SEEDS["rmat16"])
+    assert len(srcs) == 64
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    for i, src in enumerate(srcs):
+        if i % 16 == 0:
+            say(f"rmat16 source {i}")
+        parent, depth = device_bfs(gpu, g, int(src))
+        assert_valid(A, int(src), parent, depth, what="rmat16")
+
+
+def test_repeat_same_result(gpu):
+    from paper_1508_03619_amd import inputs
+    el = inputs.rmat(15, 16, seed=31)
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    src = int(inputs.pick_sources(el, 1, seed=32)[0])
+    ref = A.bfs(src)[0]
+    say("repeat x30")
+    for _ in range(30):
+        parent, depth = device_bfs(gpu, g, src)
+        assert_valid(A, src, parent, depth, ref)
+
+
+def test_two_streams_concurrently(gpu):
+    import torch
+    from paper_1508_03619_amd import inputs
+    el = inputs.rmat(15, 16, seed=41)
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    srcs = [int(x) for x in inputs.pick_sources(el, 8, seed=42)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    say("two streams")
+    for i, src in enumerate(srcs):
+        st = streams[i % 2]
+        p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(st):
+            gpu.bfs(g, src, p, d, stream=st)
+        outs.append((src, p, d))
+    torch.cuda.synchronize()
+    for src, p, d in outs:
+        assert_valid(A, src, p.cpu().numpy(), d.cpu().numpy())
+
+
+def test_grid_road_like(gpu):
+    from paper_1508_03619_amd import inputs
+    el = inputs.grid(300, 200, seed=7)
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    for src in inputs.pick_sources(el, 3, seed=8):
+        for mode in (0, 1):
+            say(f"grid300x200 src={src} mode={mode}")
+            parent, depth = device_bfs(gpu, g, int(src), params=dict(mode=mode))
+            assert_valid(A, int(src), parent, depth, what="grid")
+
+
+def test_stats_records(gpu):
+    from paper_1508_03619_amd import inputs
+    el = inputs.rmat(14, 16, seed=51)
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    src = int(inputs.pick_sources(el, 1, seed=52)[0])
+    import torch
+    dref = A.bfs(src)[0]
+    deg = np.diff(A.offsets)
+    for mode in (0, 1):
+        parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        recs = gpu.bfs(g, src, parent, depth, params=dict(mode=mode), stats=True)
+        assert len(recs) == dref.max() + 1  # levels 0..max depth; the last claims nothing
+        for r in recs:
+            dd = r["level"]
+            assert r["frontier"] == int((dref == dd).sum())
+            assert r["frontier_edges"] == int(deg[dref == dd].sum())
+            assert r["claimed"] == int((dref == dd + 1).sum())
