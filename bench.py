@@ -1,0 +1,289 @@
+"""Benchmark: direction-optimizing BFS GTEPS on one MI355X.
+
+Workload (one "step"): 64 single-source direction-optimizing searches on an
+R-MAT scale-22 graph (edge factor 16, a=.57 b=.19 c=.19) and 64 on a
+uniform-random graph with 2^22 vertices and 16*2^22 raw pairs, each from
+seeded random non-zero-degree sources (the paper's 64-trial protocol).
+Graphs are generated and built before timing (graph building is untimed in
+the paper's methodology) and stay resident in HBM.
+
+GTEPS = sum over trials of m_s / elapsed, where m_s is the number of
+undirected edges in the source's connected component.
+
+Also reported, outside the timed steps: a 64-lane batched search over the
+same sources (per-source throughput vs repeated single-source searches), the
+measured stream-copy bandwidth, the roofline of the dominant kernel and the
+CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1508_03619_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(recs, n) -> int:
+    """Bytes the search must move (per launch), from per-level records.
+
+    init: row_ptr read 8(n+1), parent+depth written 8n
+    top-down level, frontier F, N_F edges, C claimed:
+        4|F| queue + 16|F| row_ptr + 4 N_F col + 4 N_F parent probes + 12|C|
+    bottom-up level, U unvisited, S_U scanned entries, H found:
+        16|U| row_ptr + 4 S_U col + 3 n/8 bitmaps + 8|H|
+    switch to bottom-up: 4|F| + n/8; final pass: 8n
+    """
+    total = 8 * (n + 1) + 8 * n + 8 * n
+    prev_dir = 1
+    for r in recs:
+        if r["direction"] == 1:
+            total += 20 * r["frontier"] + 8 * r["frontier_edges"] + 12 * r["claimed"]
+        else:
+            if prev_dir == 1:
+                total += 4 * r["frontier"] + n // 8
+            total += 16 * r["unvisited"] + 4 * r["scanned"] + 3 * n // 8 + 8 * r["claimed"]
+        prev_dir = r["direction"]
+    return int(total)
+
+
+class GraphCase:
+    def __init__(self, name, el, gb, torch, nsrc, src_seed):
+        from paper_1508_03619_amd import inputs
+        t0 = time.time()
+        self.name = name
+        self.el = el
+        self.g = gb.build_csr(el.n, el.src, el.dst)
+        self.sources = inputs.pick_sources(el, nsrc, seed=src_seed)
+        rp, _ = self.g.export_row_ptr()
+        self.deg = np.diff(rp)
+        self.parent = torch.empty(self.g.n, dtype=torch.int32, device="cuda")
+        self.depth = torch.empty(self.g.n, dtype=torch.int32, device="cuda")
+        log(f"{name}: n={self.g.n} nnz={self.g.nnz} max_deg={int(self.deg.max())} "
+            f"built in {time.time() - t0:.1f}s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sources", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--graphs", default="rmat22,urand22")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each search runs on a single MI355X; see the sharding notes in the design).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1508_03619_amd import gapbfs as gb
+    from paper_1508_03619_amd import inputs
+
+    gb.load()
+    torch.cuda.set_device(0)
+    dev = gb.device_query()
+    log(f"device {dev['arch']} CUs={dev['compute_units']} params={gb.get_params()}")
+    stream = torch.cuda.current_stream()
+
+    cases = []
+    for name in args.graphs.split(","):
+        el = inputs.workload(name)
+        cases.append(GraphCase(name, el, gb, torch, args.sources, inputs.SOURCE_SEEDS[name]))
+
+    # Per-source component edge counts m_s and per-level records (untimed).
+    for c in cases:
+        c.ms = []
+        c.alg_bytes = []
+        c.levels = []
+        for s in c.sources:
+            recs = gb.bfs(c.g, int(s), c.parent, c.depth, stats=True)
+            d = c.depth.cpu().numpy()
+            c.ms.append(int(c.deg[d >= 0].sum()) // 2)
+            c.alg_bytes.append(algorithmic_bytes(recs, c.g.n))
+            c.levels.append(len(recs))
+        c.ms = np.array(c.ms, dtype=np.int64)
+        log(f"{c.name}: mean m_s={c.ms.mean():.3e} mean levels={np.mean(c.levels):.1f} "
+            f"dirs(first source)={[r['direction'] for r in gb.last_stats()]}")
+
+    ev_pairs = {c.name: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                         for _ in c.sources] for c in cases}
+
+    def step(record=False):
+        for c in cases:
+            for i, s in enumerate(c.sources):
+                e0, e1 = ev_pairs[c.name][i]
+                if record:
+                    e0.record(stream)
+                gb.bfs(c.g, int(s), c.parent, c.depth, stream=stream)
+                if record:
+                    e1.record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    per_trial = {c.name: [] for c in cases}
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(record=True)
+        torch.cuda.synchronize()
+        for c in cases:
+            per_trial[c.name].append([ev_pairs[c.name][i][0].elapsed_time(ev_pairs[c.name][i][1])
+                                      for i in range(len(c.sources))])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_edges = sum(int(c.ms.sum()) for c in cases) * args.steps
+    value = total_edges / wall / 1e9
+    ms_per_step = wall / args.steps * 1e3
+
+    detail = {}
+    launches = 0
+    launch_ms_sum = 0.0
+    alg_sum = 0
+    for c in cases:
+        t = np.array(per_trial[c.name])  # steps x sources, ms
+        gteps = c.ms[None, :] / (t * 1e-3) / 1e9
+        detail[c.name] = {
+            "n": int(c.g.n), "nnz": int(c.g.nnz),
+            "gteps_aggregate": float(c.ms.sum() * args.steps / (t.sum() * 1e-3) / 1e9),
+            "gteps_median_trial": float(np.median(gteps)),
+            "trial_ms_median": float(np.median(t)), "trial_ms_min": float(t.min()),
+            "trial_ms_max": float(t.max()),
+            "levels_mean": float(np.mean(c.levels)),
+            "alg_bytes_mean": float(np.mean(c.alg_bytes)),
+            "alg_gbs_median": float(np.median(np.array(c.alg_bytes)[None, :] / (t * 1e-3) / 1e9)),
+        }
+        launches += t.size
+        launch_ms_sum += float(t.sum())
+        alg_sum += int(np.sum(c.alg_bytes)) * args.steps
+    avg_launch_ms = launch_ms_sum / launches
+    avg_alg_bytes = alg_sum / launches
+    achieved = avg_alg_bytes / (avg_launch_ms * 1e-3) / 1e9
+
+    # HBM traffic from committed rocprofv3 counter runs, if they match this build.
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_k_bfs_persistent_rmat22_urand22.json")
+    if os.path.exists(tpath):
+        try:
+            tj = json.load(open(tpath))
+            if tj.get("source_hash") == kernel_source_hash():
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_bfs_persistent", "avg_launch_ms": round(avg_launch_ms, 4),
+                "alg_bytes_per_launch": int(avg_alg_bytes)}
+
+    # Measured copy bandwidth (read + write), reported beside the peak.
+    nbytes = 1 << 32
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        gb.stream_copy(b, a, nbytes)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        gb.stream_copy(b, a, nbytes)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    detail["stream_copy_gbs"] = round(copy_gbs, 1)
+
+    # Batched leg: one 64-lane launch per graph vs the same sources one by one.
+    if not args.no_batch:
+        for c in cases:
+            ns = len(c.sources)
+            parents = [torch.empty(c.g.n, dtype=torch.int32, device="cuda") for _ in range(ns)]
+            depths = [torch.empty(c.g.n, dtype=torch.int32, device="cuda") for _ in range(ns)]
+            gb.bfs_batch([c.g], [0] * ns, [int(s) for s in c.sources], parents, depths)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            reps = 3
+            for _ in range(reps):
+                gb.bfs_batch([c.g], [0] * ns, [int(s) for s in c.sources], parents, depths)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            bt = e0.elapsed_time(e1) / reps
+            single_ms = float(np.sum(np.mean(np.array(per_trial[c.name]), axis=0)))
+            detail[c.name]["batch64_ms"] = round(bt, 3)
+            detail[c.name]["batch64_gteps"] = round(float(c.ms.sum()) / (bt * 1e-3) / 1e9, 2)
+            detail[c.name]["single64_ms_sum"] = round(single_ms, 3)
+            detail[c.name]["batch_speedup_vs_single"] = round(single_ms / bt, 2)
+            del parents, depths
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        c = cases[0]
+        A = oracle.Adjacency(c.el.n, c.el.src, c.el.dst)
+        done_edges, done_t, k = 0, 0.0, 0
+        for s in c.sources:
+            t1 = time.perf_counter()
+            d, _ = A.bfs(int(s))
+            done_t += time.perf_counter() - t1
+            done_edges += int(c.deg[d >= 0].sum()) // 2
+            k += 1
+            if done_t > args.cpu_seconds:
+                break
+        cpu = {"value": round(done_edges / done_t / 1e9, 5), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle",
+               "sample": f"serial FIFO oracle, {k} of the {len(c.sources)} {c.name} sources, "
+                         f"{done_t:.1f}s (adjacency build untimed)"}
+
+    out = {
+        "metric": "BFS GTEPS (direction-optimizing, single-source)",
+        "value": round(value, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "rmat22+urand22: R-MAT scale 22 ef16 (a.57 b.19 c.19) and uniform "
+                               "2^22 x 16*2^22 pairs, symmetrised int32 CSR, 64 random non-zero-degree "
+                               "sources each, direction-optimizing single-source BFS",
+                   "sources_per_graph": args.sources, "params": gb.get_params()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -56,6 +56,41 @@ gap_status device_info(int dev, const DeviceInfo **out) {
   return GAP_OK;
 }
 
+// ---- ordering of persistent launches across streams ------------------------------
+
+struct CoopState {
+  std::mutex mu;
+  hipEvent_t ev = nullptr;
+  bool recorded = false;
+  hipStream_t last = nullptr;
+};
+static std::map<int, std::unique_ptr<CoopState>> g_coop;
+
+static CoopState *coop_state(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto &p = g_coop[dev];
+  if (!p) p.reset(new CoopState());
+  return p.get();
+}
+
+gap_status coop_begin(int dev, hipStream_t s, CoopOrder *o) {
+  CoopState *cs = coop_state(dev);
+  o->lock = std::unique_lock<std::mutex>(cs->mu);
+  if (!cs->ev) GAP_HIP(hipEventCreateWithFlags(&cs->ev, hipEventDisableTiming));
+  if (cs->recorded && cs->last != s) GAP_HIP(hipStreamWaitEvent(s, cs->ev, 0));
+  return GAP_OK;
+}
+
+gap_status coop_end(int dev, hipStream_t s, CoopOrder *o) {
+  CoopState *cs = coop_state(dev);
+  hipError_t e = hipEventRecord(cs->ev, s);
+  cs->recorded = (e == hipSuccess);
+  cs->last = s;
+  o->lock.unlock();
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return GAP_OK;
+}
+
 // ---- parameters --------------------------------------------------------------------
 
 static gap_params default_params() {
@@ -65,8 +100,8 @@ static gap_params default_params() {
   p.direction = GAP_DIR_AUTO;
   p.alpha = 15;
   p.beta = 18;
-  p.block = 256;
-  p.blocks_per_cu = 0;
+  p.block = 1024;
+  p.blocks_per_cu = 1;
   p.hub_degree = 256;
   p.chunk_edges = 256;
   p.graph_chunk = 16;
@@ -151,16 +186,25 @@ static void release_single(Workspace *ws) {
   for (auto &b : ws->bm) free_dev(b);
   free_dev(ws->depth_scratch);
   free_dev(ws->ctl);
-  if (ws->h_cnt) (void)hipHostFree(ws->h_cnt);
-  ws->h_cnt = nullptr;
+  free_dev(ws->dd_args);
+  if (ws->h_flags) (void)hipHostFree(ws->h_flags);
+  ws->h_flags = nullptr;
+  if (ws->h_args) (void)hipHostFree(ws->h_args);
+  ws->h_args = nullptr;
+  if (ws->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)ws->graph_exec);
+  ws->graph_exec = nullptr;
+  ws->graph_key = 0;
   ws->cap_n = 0;
   ws->cap_chunks = 0;
 }
 
+static constexpr size_t kArgsBytes = 1024;  // >= sizeof of the per-search argument block
+
 gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const gap_params &p) {
-  // Each vertex enters a queue at most once per search, so n slots suffice;
-  // hub chunk items are bounded by nnz/chunk + nnz/hub (one partial chunk per
-  // vertex of degree > hub, and there are at most nnz/hub of those).
+  // Each vertex enters a level's queue at most once, so a segment of n slots
+  // can take any group's share; hub chunk items per level are bounded by
+  // nnz/chunk + nnz/hub (one partial chunk per vertex of degree > hub, and
+  // there are at most nnz/hub of those).  Every group has its own segment.
   const int64_t chunks = nnz / p.chunk_edges + nnz / p.hub_degree + 2;
   if (ws->cap_n >= n && ws->cap_chunks >= chunks && ws->ctl) return GAP_OK;
   if (ws->ctl) GAP_HIP(hipStreamSynchronize(ws->stream));
@@ -170,14 +214,16 @@ gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const
   const int64_t words = (cap_n + 63) / 64 + 1;
   hipError_t e = hipSuccess;
   for (auto &q : ws->q)
-    if (e == hipSuccess) e = hipMalloc(&q, sizeof(int32_t) * (size_t)cap_n);
+    if (e == hipSuccess) e = hipMalloc(&q, sizeof(int32_t) * (size_t)cap_n * kGroups);
   for (auto &c : ws->cq)
-    if (e == hipSuccess) e = hipMalloc(&c, sizeof(int2) * (size_t)cap_c);
+    if (e == hipSuccess) e = hipMalloc(&c, sizeof(int2) * (size_t)cap_c * kGroups);
   for (auto &b : ws->bm)
     if (e == hipSuccess) e = hipMalloc(&b, sizeof(uint64_t) * (size_t)words);
   if (e == hipSuccess) e = hipMalloc(&ws->depth_scratch, sizeof(int32_t) * (size_t)cap_n);
   if (e == hipSuccess) e = hipMalloc(&ws->ctl, sizeof(Ctl));
-  if (e == hipSuccess) e = hipHostMalloc(&ws->h_cnt, sizeof(LevelCounters));
+  if (e == hipSuccess) e = hipMalloc(&ws->dd_args, kArgsBytes);
+  if (e == hipSuccess) e = hipHostMalloc(&ws->h_flags, 4 * sizeof(int));
+  if (e == hipSuccess) e = hipHostMalloc(&ws->h_args, kArgsBytes);
   if (e == hipSuccess) e = hipMemset(ws->ctl, 0, sizeof(Ctl));
   if (e != hipSuccess) {
     release_single(ws);

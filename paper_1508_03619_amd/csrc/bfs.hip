@@ -1,35 +1,38 @@
-// Single-source direction-optimizing BFS on gfx950: kernels and the two
-// level schedules (persistent cooperative kernel; one launch per step).
+// Single-source direction-optimizing BFS on gfx950: kernels and the three
+// level schedules.
+//  * persistent: one cooperative kernel runs every level; levels are
+//    separated by a reducing grid barrier;
+//  * levels: one launch per step, device-side decisions, the host waits for
+//    each level's "done" flag;
+//  * graph: the same per-level kernels captured into a hipGraph of K levels
+//    that is replayed until the device reports the search done.
 #include <algorithm>
+#include <vector>
 
 #include "bfs_kernels.h"
 #include "runtime.h"
 
 namespace gap {
 
-struct PersistArgs {
+struct SearchArgs {
   DevGraph g;
   int32_t *parent;
   int32_t *depth;
   int32_t source;
-  int32_t *q0, *q1;
-  int2 *c0, *c1;
-  uint64_t *fa, *fb, *vbm;
+  Queues Q;
+  uint64_t *bm0, *bm1;  // frontier bitmaps (current / next alternate)
+  uint64_t *vbm;
   Ctl *ctl;
   Params p;
   DevLevelRec *recs;
   int32_t max_recs;
 };
 
-__device__ inline unsigned long long ld_agent(const unsigned long long *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// ---- persistent cooperative kernel -------------------------------------------
 
-// The whole search in one cooperative launch.  Every workgroup runs the same
-// level loop and takes the same decisions from the same device counters;
-// levels are separated by grid barriers.
 template <int BLOCK, bool STATS>
-__global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
+  __shared__ Stage<BLOCK> st;
   const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
   const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int64_t nwaves = nthreads / kWave;
@@ -37,25 +40,22 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs a) {
   const unsigned int nblocks = gridDim.x;
 
   init_vertices(a.g, a.parent, a.depth, a.source, tid, nthreads);
-  if (tid == 0) init_source(a.g, a.source, a.p.hub, a.p.chunk, a.q0, a.c0, a.ctl);
-  if (!grid_barrier(a.ctl, nblocks)) return;
+  Totals part = {};
+  if (tid == 0) part = init_source(a.g, a.Q, a.ctl, a.source, a.p.hub, a.p.chunk);
+  if (!grid_sync(a.ctl, nblocks, part, 0, 0)) return;
 
   int32_t d = 0, dir = kTopDown;
   bool have_bm = false;
   int64_t mu = a.g.nnz, nf_prev = 0;
-  int32_t *qin = a.q0, *qout = a.q1;
-  int2 *cin = a.c0, *cout = a.c1;
-  uint64_t *fb = a.fa, *nb = a.fb;
+  int fsel = 0;
   for (;;) {
-    LevelCounters *prev = &a.ctl->cnt[(d + 2) % 3];
-    const int64_t nq = (int64_t)ld_agent(&prev->nq);
-    const int64_t nc = (int64_t)ld_agent(&prev->nc);
-    const int64_t nv = (int64_t)ld_agent(&prev->nv);
-    const int64_t mf = (int64_t)ld_agent(&prev->mf);
+    const Published &P = a.ctl->pub[d & 1];
+    const int64_t nv = (int64_t)ld_agent(&P.t.nv);
+    const int64_t mf = (int64_t)ld_agent(&P.t.mf);
     if (STATS && tid == 0 && d > 0 && d - 1 < a.max_recs) {
       a.recs[d - 1].claimed = (unsigned long long)nv;
-      a.recs[d - 1].scanned = ld_agent(&prev->scanned);
-      a.recs[d - 1].unvisited = ld_agent(&prev->unvisited);
+      a.recs[d - 1].scanned = ld_agent(&P.t.scanned);
+      a.recs[d - 1].unvisited = ld_agent(&P.t.unvisited);
     }
     if (nv == 0) break;
     if (d > a.g.n) {  // more levels than vertices: inconsistent counters
@@ -65,33 +65,31 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs a) {
     mu -= mf;
     const int32_t ndir = decide_direction(dir, nv, mf, mu, nf_prev, a.g.n, a.p, d);
     if (ndir == kBottomUp && !(dir == kBottomUp && have_bm)) {
-      convert_to_bitmaps(a.g, a.parent, a.depth, d, fb, a.vbm, gwave, nwaves);
-      if (!grid_barrier(a.ctl, nblocks)) return;
+      convert_to_bitmaps(a.g, a.parent, a.depth, d, (fsel ? a.bm1 : a.bm0), a.vbm, gwave, nwaves);
+      if (!grid_sync(a.ctl, nblocks, Totals{}, -1, 0)) return;
       have_bm = true;
     }
     if (ndir == kTopDown) have_bm = false;
     dir = ndir;
-    if (tid == 0) {
-      a.ctl->cnt[(d + 1) % 3] = LevelCounters();
-      if (STATS && d < a.max_recs) {
-        DevLevelRec r = {};
-        r.level = d;
-        r.direction = dir;
-        r.frontier = (unsigned long long)nv;
-        r.frontier_edges = (unsigned long long)mf;
-        a.recs[d] = r;
-      }
+    if (STATS && tid == 0 && d < a.max_recs) {
+      DevLevelRec r = {};
+      r.level = d;
+      r.direction = dir;
+      r.frontier = (unsigned long long)nv;
+      r.frontier_edges = (unsigned long long)mf;
+      a.recs[d] = r;
     }
-    StepArgs s{a.g, a.parent, a.depth, qin, cin, nq, nc, qout, cout, fb, a.vbm, nb,
-               &a.ctl->cnt[d % 3], d, a.p.hub, a.p.chunk};
+    StepArgs s{a.g, a.parent, a.depth, a.Q, d & 1, a.ctl, (fsel ? a.bm1 : a.bm0), a.vbm, (fsel ? a.bm0 : a.bm1),
+               d, a.p.hub, a.p.chunk};
+    step_begin<BLOCK>(s, st);
+    LaneAcc acc;
     if (dir == kTopDown)
-      td_step<STATS>(s, gwave, nwaves);
+      td_step<BLOCK, STATS>(s, st, acc, gwave, nwaves);
     else
-      bu_step<STATS>(s, gwave, nwaves);
-    if (!grid_barrier(a.ctl, nblocks)) return;
-    swap_ptr(qin, qout);
-    swap_ptr(cin, cout);
-    if (dir == kBottomUp) swap_ptr(fb, nb);
+      bu_step<BLOCK, STATS>(s, st, acc, gwave, nwaves);
+    const Totals t = step_end<BLOCK>(s, st, acc);
+    if (!grid_sync(a.ctl, nblocks, t, (d + 1) & 1, (d + 1) & 1)) return;
+    if (dir == kBottomUp) fsel ^= 1;
     nf_prev = nv;
     ++d;
   }
@@ -99,64 +97,137 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(PersistArgs a) {
   if (tid == 0) a.ctl->levels = d;
 }
 
-// ---- one launch per step ----------------------------------------------------
+// ---- device-driven per-level kernels (levels and graph schedules) -------------
+// The search state lives in Ctl (level, dir, done, have_bm, mu, nf_prev) and
+// the per-search arguments in device memory, so a captured graph can be
+// replayed for any source and output buffers.
 
-struct InitArgs {
-  DevGraph g;
-  int32_t *parent, *depth;
-  int32_t source, hub, chunk;
-  int32_t *q0;
-  int2 *c0;
-  Ctl *ctl;
+constexpr int kLevelBlock = 256;
+
+struct alignas(64) DDArgs {
+  SearchArgs s;
+  int fsel;          // 1 when bm1 holds the current frontier bitmap
+  int need_convert;  // the next step is bottom-up and needs the bitmaps
 };
+static_assert(sizeof(DDArgs) <= 1024, "argument block must fit the workspace slot");
 
-__global__ __launch_bounds__(256) void k_init(InitArgs a) {
+__global__ __launch_bounds__(kLevelBlock) void k_dd_init(DDArgs *A) {
+  const SearchArgs a = A->s;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   init_vertices(a.g, a.parent, a.depth, a.source, tid, nthreads);
-  if (tid == 0) init_source(a.g, a.source, a.hub, a.chunk, a.q0, a.c0, a.ctl);
+  if (tid == 0) {
+    const Totals t = init_source(a.g, a.Q, a.ctl, a.source, a.p.hub, a.p.chunk);
+    add_totals(a.ctl->grp[0], t);
+    a.ctl->level = -1;
+    a.ctl->dir = kTopDown;
+    a.ctl->have_bm = 0;
+    a.ctl->mu = a.g.nnz;
+    a.ctl->nf_prev = 0;
+    a.ctl->done = 0;
+    A->fsel = 0;
+    A->need_convert = 0;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_convert(DevGraph g, const int32_t *parent,
-                                                 const int32_t *depth, int32_t d, uint64_t *fbm,
-                                                 uint64_t *vbm) {
+// Closes level L = ctl->level (L = -1 after init): reduces the level's
+// totals, publishes F_{L+1}, and decides how level L+1 runs.  One wave:
+// lane h handles group h, lane 0 decides.
+template <bool STATS>
+__global__ __launch_bounds__(64) void k_dd_publish(DDArgs *A) {
+  const int lane = threadIdx.x;
+  const SearchArgs &a = A->s;
+  Ctl *ctl = a.ctl;
+  if (ctl->done) return;
+  const int L = ctl->level;
+  const int d = L + 1;
+  Totals p = {};
+  if (lane < kGroups) {
+    p = take_totals(ctl->grp[lane]);
+    publish_segment(ctl, d & 1, d & 1, lane);
+  }
+  Totals t;
+  t.nv = wave_sum_u64(p.nv);
+  t.mf = wave_sum_u64(p.mf);
+  t.scanned = wave_sum_u64(p.scanned);
+  t.unvisited = wave_sum_u64(p.unvisited);
+  if (lane != 0) return;
+  publish_totals(ctl, d & 1, t);
+  if (STATS && L >= 0 && L < a.max_recs) {
+    a.recs[L].claimed = t.nv;
+    a.recs[L].scanned = t.scanned;
+    a.recs[L].unvisited = t.unvisited;
+  }
+  if (L >= 0 && ctl->dir == kBottomUp) A->fsel ^= 1;
+  const int64_t nv = (int64_t)t.nv, mf = (int64_t)t.mf;
+  if (nv == 0) {
+    ctl->done = 1;
+    ctl->levels = d;
+    return;
+  }
+  if (d > a.g.n) {
+    ctl->err = GAP_EINTERNAL;
+    ctl->done = 1;
+    return;
+  }
+  ctl->mu -= mf;
+  const int32_t dir = ctl->dir;
+  const int32_t ndir = decide_direction(dir, nv, mf, ctl->mu, ctl->nf_prev, a.g.n, a.p, d);
+  A->need_convert = (ndir == kBottomUp && !(dir == kBottomUp && ctl->have_bm)) ? 1 : 0;
+  ctl->have_bm = (ndir == kBottomUp) ? 1 : 0;
+  ctl->dir = ndir;
+  ctl->nf_prev = nv;
+  ctl->level = d;
+  if (STATS && d < a.max_recs) {
+    DevLevelRec r = {};
+    r.level = d;
+    r.direction = ndir;
+    r.frontier = (unsigned long long)nv;
+    r.frontier_edges = (unsigned long long)mf;
+    a.recs[d] = r;
+  }
+}
+
+__global__ __launch_bounds__(kLevelBlock) void k_dd_convert(DDArgs *A) {
+  const SearchArgs &a = A->s;
+  if (a.ctl->done || !A->need_convert) return;
   const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
   const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  convert_to_bitmaps(g, parent, depth, d, fbm, vbm, gwave, nwaves);
+  convert_to_bitmaps(a.g, a.parent, a.depth, a.ctl->level, (A->fsel ? a.bm1 : a.bm0), a.vbm, gwave, nwaves);
 }
 
 template <bool STATS>
-__global__ __launch_bounds__(256) void k_td(StepArgs a) {
+__global__ __launch_bounds__(kLevelBlock) void k_dd_step(DDArgs *A) {
+  __shared__ Stage<kLevelBlock> st;
+  const SearchArgs &a = A->s;
+  if (a.ctl->done) return;
+  const int d = a.ctl->level;
+  const int fsel = A->fsel;
   const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
   const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  td_step<STATS>(a, gwave, nwaves);
+  StepArgs s{a.g, a.parent, a.depth, a.Q, d & 1, a.ctl, (fsel ? a.bm1 : a.bm0), a.vbm, (fsel ? a.bm0 : a.bm1),
+             d, a.p.hub, a.p.chunk};
+  step_begin<kLevelBlock>(s, st);
+  LaneAcc acc;
+  if (a.ctl->dir == kTopDown)
+    td_step<kLevelBlock, STATS>(s, st, acc, gwave, nwaves);
+  else
+    bu_step<kLevelBlock, STATS>(s, st, acc, gwave, nwaves);
+  const Totals t = step_end<kLevelBlock>(s, st, acc);
+  if (threadIdx.x == 0) add_totals(a.ctl->grp[blockIdx.x % kGroups], t);
 }
 
-template <bool STATS>
-__global__ __launch_bounds__(256) void k_bu(StepArgs a) {
-  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-  const int64_t gwave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  bu_step<STATS>(a, gwave, nwaves);
-}
-
-__global__ __launch_bounds__(256) void k_fixup(int64_t n, int32_t *parent) {
+__global__ __launch_bounds__(kLevelBlock) void k_dd_fixup(DDArgs *A) {
+  const SearchArgs &a = A->s;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  fixup_parents(n, parent, tid, nthreads);
+  fixup_parents(a.g.n, a.parent, tid, nthreads);
 }
 
 // ---- host side ----------------------------------------------------------------
 
-static int grid_for_waves(int64_t waves, int block) {
-  const int64_t wpb = block / kWave;
-  int64_t b = (waves + wpb - 1) / wpb;
-  if (b < 1) b = 1;
-  if (b > 65536) b = 65536;
-  return (int)b;
-}
-
 template <int BLOCK, bool STATS>
-static gap_status launch_persistent(const PersistArgs &a, const DeviceInfo *di, int blocks_per_cu,
+static gap_status launch_persistent(const SearchArgs &a, const DeviceInfo *di, int blocks_per_cu,
                                     hipStream_t stream) {
   auto kern = k_bfs_persistent<BLOCK, STATS>;
   int per_cu = 0;
@@ -167,7 +238,7 @@ static gap_status launch_persistent(const PersistArgs &a, const DeviceInfo *di, 
   }
   if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
   const int grid = per_cu * di->cus;
-  PersistArgs args = a;
+  SearchArgs args = a;
   void *kargs[] = {&args};
   GAP_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(BLOCK), kargs, 0,
                                      stream));
@@ -175,7 +246,7 @@ static gap_status launch_persistent(const PersistArgs &a, const DeviceInfo *di, 
 }
 
 template <bool STATS>
-static gap_status dispatch_persistent(const PersistArgs &a, const DeviceInfo *di,
+static gap_status dispatch_persistent(const SearchArgs &a, const DeviceInfo *di,
                                       const gap_params &p, hipStream_t stream) {
   switch (p.block) {
     case 256: return launch_persistent<256, STATS>(a, di, p.blocks_per_cu, stream);
@@ -184,80 +255,118 @@ static gap_status dispatch_persistent(const PersistArgs &a, const DeviceInfo *di
   }
 }
 
-static gap_status run_levels(const PersistArgs &a, bool stats, Workspace *ws, hipStream_t stream,
-                             int32_t *levels_out, std::vector<DevLevelRec> *host_recs) {
-  const int block = 256;
-  const int64_t n = a.g.n;
-  const int64_t nwords = (n + kWave - 1) / kWave;
-  InitArgs ia{a.g, a.parent, a.depth, a.source, a.p.hub, a.p.chunk, a.q0, a.c0, a.ctl};
-  k_init<<<grid_for_waves((n + kWave - 1) / kWave, block), block, 0, stream>>>(ia);
-  GAP_HIP(hipGetLastError());
-  int32_t d = 0, dir = kTopDown;
-  bool have_bm = false;
-  int64_t mu = a.g.nnz, nf_prev = 0;
-  int32_t *qin = a.q0, *qout = a.q1;
-  int2 *cin = a.c0, *cout = a.c1;
-  uint64_t *fb = a.fa, *nb = a.fb;
-  for (;;) {
-    GAP_HIP(hipMemcpyAsync(ws->h_cnt, &a.ctl->cnt[(d + 2) % 3], sizeof(LevelCounters),
-                           hipMemcpyDeviceToHost, stream));
-    GAP_HIP(hipStreamSynchronize(stream));
-    const LevelCounters c = *ws->h_cnt;
-    if (stats && d > 0 && d - 1 < (int32_t)host_recs->size()) {
-      DevLevelRec &h = (*host_recs)[d - 1];
-      h.claimed = c.nv;
-      h.scanned = c.scanned;
-      h.unvisited = c.unvisited;
-    }
-    const int64_t nv = (int64_t)c.nv, mf = (int64_t)c.mf;
-    if (nv == 0) break;
-    if (d > n) {
-      set_error("search ran more levels than vertices (inconsistent counters)");
-      return GAP_EINTERNAL;
-    }
-    mu -= mf;
-    const int32_t ndir = decide_direction(dir, nv, mf, mu, nf_prev, n, a.p, d);
-    if (ndir == kBottomUp && !(dir == kBottomUp && have_bm)) {
-      k_convert<<<grid_for_waves(nwords, block), block, 0, stream>>>(a.g, a.parent, a.depth, d, fb,
-                                                                     a.vbm);
-      GAP_HIP(hipGetLastError());
-      have_bm = true;
-    }
-    if (ndir == kTopDown) have_bm = false;
-    dir = ndir;
-    GAP_HIP(hipMemsetAsync(&a.ctl->cnt[(d + 1) % 3], 0, sizeof(LevelCounters), stream));
-    if (stats && d < a.max_recs) {
-      DevLevelRec h = {};
-      h.level = d;
-      h.direction = dir;
-      h.frontier = (unsigned long long)nv;
-      h.frontier_edges = (unsigned long long)mf;
-      host_recs->push_back(h);
-    }
-    StepArgs s{a.g, a.parent, a.depth, qin, cin, (int64_t)c.nq, (int64_t)c.nc, qout, cout, fb,
-               a.vbm, nb, &a.ctl->cnt[d % 3], d, a.p.hub, a.p.chunk};
-    if (dir == kTopDown) {
-      const int64_t waves = std::max<int64_t>((int64_t)c.nc, ((int64_t)c.nq + kWave - 1) / kWave);
-      if (stats)
-        k_td<true><<<grid_for_waves(waves, block), block, 0, stream>>>(s);
-      else
-        k_td<false><<<grid_for_waves(waves, block), block, 0, stream>>>(s);
-    } else {
-      if (stats)
-        k_bu<true><<<grid_for_waves(nwords, block), block, 0, stream>>>(s);
-      else
-        k_bu<false><<<grid_for_waves(nwords, block), block, 0, stream>>>(s);
-    }
-    GAP_HIP(hipGetLastError());
-    swap_ptr(qin, qout);
-    swap_ptr(cin, cout);
-    if (dir == kBottomUp) swap_ptr(fb, nb);
-    nf_prev = nv;
-    ++d;
+// Grid of the per-level kernels: enough waves to cover the largest step
+// (one wave per 64-vertex word), capped so the launch stays cheap.
+static int level_grid(const DeviceInfo *di, int64_t n) {
+  const int64_t words = (n + kWave - 1) / kWave;
+  const int64_t wpb = kLevelBlock / kWave;
+  int64_t b = (words + wpb - 1) / wpb;
+  const int64_t cap = (int64_t)di->cus * 8;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+static gap_status enqueue_level(DDArgs *dA, int grid, bool stats, hipStream_t stream) {
+  k_dd_convert<<<grid, kLevelBlock, 0, stream>>>(dA);
+  if (stats) {
+    k_dd_step<true><<<grid, kLevelBlock, 0, stream>>>(dA);
+    k_dd_publish<true><<<1, 64, 0, stream>>>(dA);
+  } else {
+    k_dd_step<false><<<grid, kLevelBlock, 0, stream>>>(dA);
+    k_dd_publish<false><<<1, 64, 0, stream>>>(dA);
   }
-  k_fixup<<<grid_for_waves(nwords, block), block, 0, stream>>>(n, a.parent);
   GAP_HIP(hipGetLastError());
-  *levels_out = d;
+  return GAP_OK;
+}
+
+// Reads err, levels and done from the device (synchronous).
+static gap_status read_flags(Workspace *ws, hipStream_t stream, int *done, int *levels, int *err) {
+  static_assert(offsetof(Ctl, levels) == offsetof(Ctl, err) + sizeof(int), "Ctl layout");
+  static_assert(offsetof(Ctl, done) == offsetof(Ctl, err) + 2 * sizeof(int), "Ctl layout");
+  GAP_HIP(hipMemcpyAsync(ws->h_flags, &ws->ctl->err, 3 * sizeof(int), hipMemcpyDeviceToHost,
+                         stream));
+  GAP_HIP(hipStreamSynchronize(stream));
+  *err = ws->h_flags[0];
+  *levels = ws->h_flags[1];
+  *done = ws->h_flags[2];
+  return GAP_OK;
+}
+
+static gap_status run_device_driven(const SearchArgs &a, const gap_params &p, bool stats,
+                                    Workspace *ws, const DeviceInfo *di, hipStream_t stream,
+                                    int32_t *levels_out) {
+  DDArgs *dA = reinterpret_cast<DDArgs *>(ws->dd_args);
+  // the arguments travel through pinned memory so the copy is truly async;
+  // wait first: the previous search on this stream may still read it
+  GAP_HIP(hipStreamSynchronize(stream));
+  DDArgs *pin = reinterpret_cast<DDArgs *>(ws->h_args);
+  *pin = DDArgs{};
+  pin->s = a;
+  GAP_HIP(hipMemcpyAsync(dA, pin, sizeof(DDArgs), hipMemcpyHostToDevice, stream));
+  GAP_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), stream));
+  const int grid = level_grid(di, a.g.n);
+  k_dd_init<<<grid, kLevelBlock, 0, stream>>>(dA);
+  if (stats)
+    k_dd_publish<true><<<1, 64, 0, stream>>>(dA);
+  else
+    k_dd_publish<false><<<1, 64, 0, stream>>>(dA);
+  GAP_HIP(hipGetLastError());
+  int done = 0, levels = 0, err = 0;
+  if (p.mode == GAP_MODE_LEVELS) {
+    for (int64_t it = 0;; ++it) {
+      gap_status st = read_flags(ws, stream, &done, &levels, &err);
+      if (st != GAP_OK) return st;
+      if (done || err) break;
+      if (it > a.g.n + 1) {
+        set_error("search ran more levels than vertices");
+        return GAP_EINTERNAL;
+      }
+      st = enqueue_level(dA, grid, stats, stream);
+      if (st != GAP_OK) return st;
+    }
+  } else {
+    // hipGraph of K levels, captured once per workspace, chunk size and grid
+    const int K = p.graph_chunk;
+    const int key = K * 4 + (stats ? 2 : 0) + 1;
+    if (!ws->graph_exec || ws->graph_key != key || ws->graph_grid != grid) {
+      if (ws->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)ws->graph_exec);
+      ws->graph_exec = nullptr;
+      hipStream_t cap = nullptr;
+      GAP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        for (int k = 0; k < K; ++k) (void)enqueue_level(dA, grid, stats, cap);
+        e = hipStreamEndCapture(cap, &graph);
+      }
+      hipGraphExec_t exec = nullptr;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cap);
+      if (e != hipSuccess) return hip_fail(e, "capturing the level graph");
+      ws->graph_exec = exec;
+      ws->graph_key = key;
+      ws->graph_grid = grid;
+    }
+    for (int64_t it = 0;; ++it) {
+      gap_status st = read_flags(ws, stream, &done, &levels, &err);
+      if (st != GAP_OK) return st;
+      if (done || err) break;
+      if (it * K > a.g.n + 1) {
+        set_error("search ran more levels than vertices");
+        return GAP_EINTERNAL;
+      }
+      GAP_HIP(hipGraphLaunch((hipGraphExec_t)ws->graph_exec, stream));
+    }
+  }
+  if (err) {
+    set_error("device reported an inconsistent search state");
+    return GAP_EINTERNAL;
+  }
+  k_dd_fixup<<<grid, kLevelBlock, 0, stream>>>(dA);
+  GAP_HIP(hipGetLastError());
+  *levels_out = levels;
   return GAP_OK;
 }
 
@@ -280,51 +389,55 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
     st = workspace_reserve_recs(ws, max_levels);
     if (st != GAP_OK) return st;
   }
-  PersistArgs a{};
+  SearchArgs a{};
   a.g = DevGraph{g->row_ptr, g->col, g->n, g->nnz};
   a.parent = parent;
   a.depth = depth ? depth : ws->depth_scratch;
   a.source = source;
-  a.q0 = ws->q[0];
-  a.q1 = ws->q[1];
-  a.c0 = ws->cq[0];
-  a.c1 = ws->cq[1];
-  a.fa = ws->bm[0];
-  a.fb = ws->bm[1];
+  a.Q.q0 = ws->q[0];
+  a.Q.q1 = ws->q[1];
+  a.Q.c0 = ws->cq[0];
+  a.Q.c1 = ws->cq[1];
+  a.Q.n = ws->cap_n;
+  a.Q.ccap = ws->cap_chunks;
+  a.bm0 = ws->bm[0];
+  a.bm1 = ws->bm[1];
   a.vbm = ws->bm[2];
   a.ctl = ws->ctl;
   a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges};
   a.recs = want_stats ? ws->recs : nullptr;
   a.max_recs = want_stats ? max_levels : 0;
 
-  int32_t levels = 0;
-  std::vector<DevLevelRec> recs;
-  const bool host_loop = p.mode == GAP_MODE_LEVELS || p.mode == GAP_MODE_GRAPH;
-  if (host_loop) {
-    st = run_levels(a, want_stats, ws, stream, &levels, &recs);
+  int32_t levels = -1;
+  const bool device_driven = p.mode == GAP_MODE_LEVELS || p.mode == GAP_MODE_GRAPH;
+  if (device_driven) {
+    st = run_device_driven(a, p, want_stats, ws, di, stream, &levels);
     if (st != GAP_OK) return st;
   } else {
     GAP_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), stream));
+    CoopOrder order;
+    st = coop_begin(g->device, stream, &order);
+    if (st != GAP_OK) return st;
     st = want_stats ? dispatch_persistent<true>(a, di, p, stream)
                     : dispatch_persistent<false>(a, di, p, stream);
+    gap_status st2 = coop_end(g->device, stream, &order);
     if (st != GAP_OK) return st;
+    if (st2 != GAP_OK) return st2;
   }
   if (want_stats) {
-    GAP_HIP(hipStreamSynchronize(stream));
-    if (!host_loop) {
-      Ctl h;
-      GAP_HIP(hipMemcpy(&h, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-      if (h.err != 0) {
-        set_error(h.err == GAP_ETIMEOUT ? "device-side wait timed out (grid barrier)"
-                                         : "search ran more levels than vertices");
-        return h.err;
-      }
-      levels = h.levels;
-      recs.resize((size_t)std::min(levels, max_levels));
-      if (!recs.empty())
-        GAP_HIP(hipMemcpy(recs.data(), ws->recs, recs.size() * sizeof(DevLevelRec),
-                          hipMemcpyDeviceToHost));
+    int done = 0, err = 0, lv = 0;
+    st = read_flags(ws, stream, &done, &lv, &err);
+    if (st != GAP_OK) return st;
+    if (err != 0) {
+      set_error(err == GAP_ETIMEOUT ? "device-side wait timed out (grid barrier)"
+                                    : "search ran more levels than vertices");
+      return err;
     }
+    levels = lv;
+    std::vector<DevLevelRec> recs((size_t)std::max(0, std::min(levels, max_levels)));
+    if (!recs.empty())
+      GAP_HIP(hipMemcpy(recs.data(), ws->recs, recs.size() * sizeof(DevLevelRec),
+                        hipMemcpyDeviceToHost));
     for (size_t i = 0; i < recs.size(); ++i) {
       stats[i].level = recs[i].level;
       stats[i].direction = recs[i].direction;
@@ -334,10 +447,8 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
       stats[i].scanned = (int64_t)recs[i].scanned;
       stats[i].unvisited = (int64_t)recs[i].unvisited;
     }
-    if (num_levels) *num_levels = levels;
-  } else if (num_levels) {
-    *num_levels = host_loop ? levels : -1;
   }
+  if (num_levels) *num_levels = levels;
   return GAP_OK;
 }
 

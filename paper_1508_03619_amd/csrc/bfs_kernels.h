@@ -1,77 +1,146 @@
 // Single-source direction-optimizing BFS: the per-level steps as device
-// functions.  They are shared by the persistent cooperative kernel and by
-// the one-launch-per-step kernels, so both schedules run the same code.
+// functions, shared by the persistent cooperative kernel and by the
+// one-launch-per-step kernels, so every schedule runs the same code.
 #pragma once
 
 #include "common.h"
 
 namespace gap {
 
+// Queue storage of one search.  The frontier F_d lives in buffer set bs =
+// d & 1 as kGroups segments: vertex segment h is q[bs] + h * n, hub chunk
+// segment h is c[bs] + h * ccap.  Segment sizes are published at the level
+// boundary (Published::q / ::c).
+struct Queues {
+  int32_t *q0, *q1;  // vertex queues of buffer sets 0 and 1
+  int2 *c0, *c1;     // hub chunk queues of buffer sets 0 and 1
+  int64_t n;         // capacity of a vertex segment
+  int64_t ccap;      // capacity of a chunk segment
+  // Selected with a conditional, not an array index: a runtime index into
+  // a pointer array would move the argument block to scratch memory.
+  __device__ int32_t *qs(int bs) const { return bs ? q1 : q0; }
+  __device__ int2 *cs(int bs) const { return bs ? c1 : c0; }
+};
+
+// Per-workgroup staging of appended vertices in LDS: a wave reserves slots
+// with one LDS atomic; the workgroup copies the slots out with one device
+// atomic per segment at the end of the step.  Slots beyond the capacity go
+// straight to the segment (reserved with a device atomic).
+template <int BLOCK>
+struct Stage {
+  static constexpr int QCAP = BLOCK * 8;
+  static constexpr int CCAP = 256;
+  int32_t q[QCAP];
+  int2 c[CCAP];
+  unsigned int qn, cn;
+  unsigned long long qbase, cbase;
+  unsigned long long qpre[kGroups + 1];  // input segment prefix sums
+  unsigned long long cpre[kGroups + 1];
+  unsigned long long part[BLOCK / kWave][4];
+};
+
 struct StepArgs {
   DevGraph g;
   int32_t *parent;       // int32[n]: -degree (or kIsolated) while unvisited
   int32_t *depth;        // int32[n]
-  const int32_t *qin;    // F_d as a vertex queue (vertices of degree <= hub)
-  const int2 *cin;       // F_d hub work items: {vertex, chunk index}
-  int64_t nq_in, nc_in;
-  int32_t *qout;         // F_{d+1} vertex queue
-  int2 *cout;            // F_{d+1} hub work items
+  Queues Q;
+  int bs_in;             // buffer set holding F_d
+  Ctl *ctl;
   const uint64_t *fbm;   // F_d bitmap (bottom-up)
   uint64_t *vbm;         // visited bitmap (bottom-up), padding bits set
   uint64_t *nbm;         // F_{d+1} bitmap written by bottom-up
-  LevelCounters *acc;    // totals of this level
   int32_t d;             // depth of the frontier being expanded
   int32_t hub;           // degree above which a vertex becomes chunk items
   int32_t chunk;         // edges per chunk item (multiple of 64)
 };
 
-// Per-lane totals carried through a step and flushed once per wave.
 struct LaneAcc {
   unsigned long long mf = 0, nv = 0, scanned = 0, unvisited = 0;
 };
 
-// Claim v for parent u (top-down).  The parent array holds -degree for an
-// unvisited vertex (Section 3, BFS), so the winner learns deg(v) from the
-// value it replaced: the frontier's edge total accrues at no extra cost.
-__device__ inline bool td_claim(const StepArgs &a, int32_t v, int32_t u, int64_t &degv) {
-  int32_t p = a.parent[v];
-  if (p >= 0) return false;
-  int32_t old = atomicCAS(&a.parent[v], p, u);
-  if (old != p) return false;
-  a.depth[v] = a.d + 1;
-  degv = (p == kIsolated) ? 0 : -(int64_t)p;
-  return true;
+// Segment holding global index i of a segmented queue (prefix in LDS).
+__device__ inline int seg_of(unsigned long long i, const unsigned long long *pre) {
+  int h = 0;
+#pragma unroll
+  for (int s = kGroups / 2; s >= 1; s >>= 1)
+    if (pre[h + s] <= i) h += s;
+  return h;
 }
 
-// Append the vertices this wave claimed to the next frontier: vertices of
-// degree <= hub go to the vertex queue, larger ones become chunk items of
-// `chunk` edges each so that one hub is expanded by many waves.  One atomic
-// per wave per queue.
-__device__ inline void wave_append(const StepArgs &a, bool claimed, int32_t v, int64_t degv,
-                                   LaneAcc &acc) {
+// Append this wave's newly reached vertices to F_{d+1}: degree <= hub ->
+// vertex queue, larger -> ceil(deg/chunk) chunk items so that one hub is
+// expanded by many waves.
+template <int BLOCK>
+__device__ inline void stage_append(const StepArgs &a, Stage<BLOCK> &st, bool claimed, int32_t v,
+                                    int64_t degv, LaneAcc &acc) {
   const uint64_t any = __ballot(claimed);
   if (any == 0) return;
   const int lane = lane_id();
+  const int g = (int)(blockIdx.x % kGroups);
+  const int bs_out = a.bs_in ^ 1;
   const bool big = claimed && degv > a.hub;
   const bool small = claimed && !big;
   const uint64_t ms = __ballot(small);
   if (ms) {
     const int leader = first_lane(ms);
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(&a.acc->nq, (unsigned long long)__popcll(ms));
+    const unsigned int cnt = (unsigned int)__popcll(ms);
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(&st.qn, cnt);
     base = __shfl(base, leader, kWave);
-    if (small) a.qout[base + lane_rank(ms)] = v;
+    const unsigned int cap = Stage<BLOCK>::QCAP;
+    const unsigned int ov_start = base > cap ? base : cap;
+    const unsigned int n_ov = base + cnt > cap ? base + cnt - ov_start : 0u;
+    unsigned long long gbase = 0;
+    if (n_ov) {
+      if (lane == leader) gbase = atomicAdd(&a.ctl->seg[bs_out][g].q, (unsigned long long)n_ov);
+      gbase = __shfl(gbase, leader, kWave);
+    }
+    if (small) {
+      const unsigned int slot = base + lane_rank(ms);
+      if (slot < cap)
+        st.q[slot] = v;
+      else
+        a.Q.qs(bs_out)[g * a.Q.n + (int64_t)(gbase + (slot - ov_start))] = v;
+    }
   }
   const uint64_t mb = __ballot(big);
   if (mb) {
-    uint32_t nch = big ? (uint32_t)((degv + a.chunk - 1) / a.chunk) : 0u;
+    // hubs: ceil(deg/chunk) items each, written by the whole wave (item i
+    // belongs to the lane whose prefix range holds i) so no lane loops alone
+    const uint32_t nch = big ? (uint32_t)((degv + a.chunk - 1) / a.chunk) : 0u;
     uint32_t total;
-    uint32_t off = wave_excl_scan_u32(nch, total);
+    const uint32_t off = wave_excl_scan_u32(nch, total);
     const int leader = first_lane(mb);
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(&a.acc->nc, (unsigned long long)total);
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(&st.cn, total);
     base = __shfl(base, leader, kWave);
-    for (uint32_t k = 0; k < nch; ++k) a.cout[base + off + k] = make_int2(v, (int)k);
+    const unsigned int cap = Stage<BLOCK>::CCAP;
+    const unsigned int ov_start = base > cap ? base : cap;
+    const unsigned int n_ov = base + total > cap ? base + total - ov_start : 0u;
+    unsigned long long gbase = 0;
+    if (n_ov) {
+      if (lane == leader) gbase = atomicAdd(&a.ctl->seg[bs_out][g].c, (unsigned long long)n_ov);
+      gbase = __shfl(gbase, leader, kWave);
+    }
+    for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+      const uint32_t i = i0 + (uint32_t)lane;
+      int j = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const uint32_t oc = __shfl(off, j + step, kWave);
+        if (oc <= i) j += step;  // largest j with off_j <= i owns item i
+      }
+      const int32_t vj = __shfl(v, j, kWave);
+      const uint32_t oj = __shfl(off, j, kWave);
+      if (i < total) {
+        const unsigned int slot = base + i;
+        const int2 item = make_int2(vj, (int)(i - oj));
+        if (slot < cap)
+          st.c[slot] = item;
+        else
+          a.Q.cs(bs_out)[g * a.Q.ccap + (int64_t)(gbase + (slot - ov_start))] = item;
+      }
+    }
   }
   if (claimed) {
     acc.mf += (unsigned long long)degv;
@@ -79,138 +148,271 @@ __device__ inline void wave_append(const StepArgs &a, bool claimed, int32_t v, i
   }
 }
 
-template <bool STATS>
-__device__ inline void flush_acc(const StepArgs &a, LaneAcc &acc) {
-  unsigned long long mf = wave_sum_u64(acc.mf);
-  unsigned long long nv = wave_sum_u64(acc.nv);
-  if (lane_id() == 0) {
-    if (mf) atomicAdd(&a.acc->mf, mf);
-    if (nv) atomicAdd(&a.acc->nv, nv);
+// Start of a step (all threads): load the input segment prefix sums of
+// pub[d & 1] and clear the staging counters.
+template <int BLOCK>
+__device__ inline void step_begin(const StepArgs &a, Stage<BLOCK> &st) {
+  if (threadIdx.x < kWave) {
+    // lane h < kGroups loads segment h's sizes: one round trip, not 2*kGroups
+    const int lane = threadIdx.x;
+    const Published &P = a.ctl->pub[a.d & 1];
+    const uint32_t q = lane < kGroups ? (uint32_t)ld_agent(&P.q[lane]) : 0u;
+    const uint32_t c = lane < kGroups ? (uint32_t)ld_agent(&P.c[lane]) : 0u;
+    uint32_t tq, tc;
+    const uint32_t oq = wave_excl_scan_u32(q, tq);
+    const uint32_t oc = wave_excl_scan_u32(c, tc);
+    if (lane <= kGroups) {
+      st.qpre[lane] = lane < kGroups ? oq : tq;
+      st.cpre[lane] = lane < kGroups ? oc : tc;
+    }
+    if (lane == 0) {
+      st.qn = 0;
+      st.cn = 0;
+    }
   }
-  if (STATS) {
-    unsigned long long sc = wave_sum_u64(acc.scanned);
-    unsigned long long un = wave_sum_u64(acc.unvisited);
-    if (lane_id() == 0) {
-      if (sc) atomicAdd(&a.acc->scanned, sc);
-      if (un) atomicAdd(&a.acc->unvisited, un);
+  __syncthreads();
+}
+
+// End of a step (all threads): copy staged vertices to this group's
+// segments (one device atomic per segment per workgroup) and reduce the
+// workgroup's totals into thread 0.
+template <int BLOCK>
+__device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc) {
+  const unsigned long long s0 = wave_sum_u64(acc.mf), s1 = wave_sum_u64(acc.nv);
+  const unsigned long long s2 = wave_sum_u64(acc.scanned), s3 = wave_sum_u64(acc.unvisited);
+  const int wv = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    st.part[wv][0] = s0;
+    st.part[wv][1] = s1;
+    st.part[wv][2] = s2;
+    st.part[wv][3] = s3;
+  }
+  __syncthreads();
+  const int g = (int)(blockIdx.x % kGroups);
+  const int bs_out = a.bs_in ^ 1;
+  const unsigned int nq = st.qn < (unsigned)Stage<BLOCK>::QCAP ? st.qn : Stage<BLOCK>::QCAP;
+  const unsigned int nc = st.cn < (unsigned)Stage<BLOCK>::CCAP ? st.cn : Stage<BLOCK>::CCAP;
+  if (threadIdx.x == 0) {
+    st.qbase = nq ? atomicAdd(&a.ctl->seg[bs_out][g].q, (unsigned long long)nq) : 0ull;
+    st.cbase = nc ? atomicAdd(&a.ctl->seg[bs_out][g].c, (unsigned long long)nc) : 0ull;
+  }
+  __syncthreads();
+  int32_t *qdst = a.Q.qs(bs_out) + g * a.Q.n + (int64_t)st.qbase;
+  for (unsigned int i = threadIdx.x; i < nq; i += BLOCK) qdst[i] = st.q[i];
+  int2 *cdst = a.Q.cs(bs_out) + g * a.Q.ccap + (int64_t)st.cbase;
+  for (unsigned int i = threadIdx.x; i < nc; i += BLOCK) cdst[i] = st.c[i];
+  Totals t = {};
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < BLOCK / kWave; ++w) {
+      t.mf += st.part[w][0];
+      t.nv += st.part[w][1];
+      t.scanned += st.part[w][2];
+      t.unvisited += st.part[w][3];
     }
   }
   acc = LaneAcc();
+  return t;
+}
+
+// Tries the claims (v[k] for parent u[k], v[k] < 0 = no edge) of four edge
+// batches at once: the parent probes, then the CAS claims, are issued
+// back-to-back so their latencies overlap; then the winners are appended.
+template <int BLOCK, bool STATS>
+__device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
+                                 const int32_t (&v)[4], const int32_t (&u)[4]) {
+  int32_t p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = v[k] >= 0 ? a.parent[v[k]] : 0;
+  bool claimed[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    claimed[k] = false;
+    if (v[k] >= 0 && p[k] < 0) claimed[k] = atomicCAS(&a.parent[v[k]], p[k], u[k]) == p[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int64_t degv = 0;
+    if (claimed[k]) {
+      a.depth[v[k]] = a.d + 1;
+      degv = (p[k] == kIsolated) ? 0 : -(int64_t)p[k];
+    }
+    if (STATS && v[k] >= 0) acc.scanned += 1;
+    stage_append<BLOCK>(a, st, claimed[k], v[k], degv, acc);
+  }
 }
 
 // Top-down step: every edge (u, v) with u in F_d is tried once.
-//  * hub chunk items: one wave walks `chunk` consecutive edges of one hub;
+//  * hub chunk items: one wave walks `chunk` consecutive edges of one hub,
+//    256 edges per round;
 //  * queue vertices: a wave takes 64 queued vertices, prefix-sums their
-//    degrees and then walks the combined edge range 64 edges at a time,
-//    each lane finding its owner vertex by a binary search over the 64
-//    offsets held in registers (no lane idles on a short list).
-template <bool STATS>
-__device__ void td_step(const StepArgs &a, int64_t gwave, int64_t nwaves) {
+//    degrees and walks the combined edge range 256 edges per round, each
+//    lane finding the owner vertex of its edges by a binary search over the
+//    64 offsets held in registers (no lane idles on a short list).
+template <int BLOCK, bool STATS>
+__device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
+                        int64_t nwaves) {
   const int lane = lane_id();
-  LaneAcc acc;
-  for (int64_t ci = gwave; ci < a.nc_in; ci += nwaves) {
-    const int2 it = a.cin[ci];
-    const int32_t u = it.x;
-    const int64_t rbeg = a.g.row_ptr[u], rend = a.g.row_ptr[u + 1];
+  const int2 *cin = a.Q.cs(a.bs_in);
+  const int32_t *qin = a.Q.qs(a.bs_in);
+  const unsigned long long nc = st.cpre[kGroups];
+  for (unsigned long long ci = (unsigned long long)gwave; ci < nc; ci += (unsigned long long)nwaves) {
+    const int h = seg_of(ci, st.cpre);
+    const int2 it = cin[h * a.Q.ccap + (int64_t)(ci - st.cpre[h])];
+    const int32_t uu = it.x;
+    const int64_t rbeg = a.g.row_ptr[uu], rend = a.g.row_ptr[uu + 1];
     const int64_t beg = rbeg + (int64_t)it.y * a.chunk;
     const int64_t end = beg + a.chunk < rend ? beg + a.chunk : rend;
-    for (int64_t e0 = beg; e0 < end; e0 += kWave) {
-      const int64_t e = e0 + lane;
-      bool claimed = false;
-      int32_t v = -1;
-      int64_t degv = 0;
-      if (e < end) {
-        v = a.g.col[e];
-        claimed = td_claim(a, v, u, degv);
-        if (STATS) acc.scanned += 1;
+    for (int64_t e0 = beg; e0 < end; e0 += 4 * kWave) {
+      int32_t v[4], u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t e = e0 + k * kWave + lane;
+        v[k] = e < end ? a.g.col[e] : -1;
+        u[k] = uu;
       }
-      wave_append(a, claimed, v, degv, acc);
+      td_claim4<BLOCK, STATS>(a, st, acc, v, u);
     }
   }
-  const int64_t ngroups = (a.nq_in + kWave - 1) / kWave;
-  for (int64_t gi = gwave; gi < ngroups; gi += nwaves) {
-    const int64_t idx = gi * kWave + lane;
-    int32_t u = -1;
+  // Vertices per wave: up to 64, fewer when the frontier is small so that
+  // every wave gets work (a small frontier on a few waves would run many
+  // dependent rounds on each).
+  const unsigned long long nq = st.qpre[kGroups];
+  unsigned long long per = (nq + (unsigned long long)nwaves - 1) / (unsigned long long)nwaves;
+  per = per < 1 ? 1 : (per > (unsigned long long)kWave ? (unsigned long long)kWave : per);
+  const unsigned long long ngroups = (nq + per - 1) / per;
+  for (unsigned long long gi = (unsigned long long)gwave; gi < ngroups;
+       gi += (unsigned long long)nwaves) {
+    const unsigned long long idx = gi * per + lane;
+    int32_t uo = -1;
     int64_t beg = 0;
     uint32_t deg = 0;
-    if (idx < a.nq_in) {
-      u = a.qin[idx];
-      beg = a.g.row_ptr[u];
-      deg = (uint32_t)(a.g.row_ptr[u + 1] - beg);
+    if ((unsigned long long)lane < per && idx < nq) {
+      const int h = seg_of(idx, st.qpre);
+      uo = qin[h * a.Q.n + (int64_t)(idx - st.qpre[h])];
+      beg = a.g.row_ptr[uo];
+      deg = (uint32_t)(a.g.row_ptr[uo + 1] - beg);
     }
     uint32_t total;
     const uint32_t off = wave_excl_scan_u32(deg, total);
-    for (uint32_t b = 0; b < total; b += kWave) {
-      const uint32_t e = b + (uint32_t)lane;
-      int j = 0;
+    for (uint32_t b = 0; b < total; b += 4 * kWave) {
+      int32_t v[4], u[4];
+      int64_t ea[4];
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        uint32_t oc = __shfl(off, j + step, kWave);
-        if (oc <= e) j += step;
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t e = b + (uint32_t)(k * kWave + lane);
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          uint32_t oc = __shfl(off, j + step, kWave);
+          if (oc <= e) j += step;
+        }
+        u[k] = __shfl(uo, j, kWave);
+        const int64_t bj = __shfl(beg, j, kWave);
+        const uint32_t oj = __shfl(off, j, kWave);
+        ea[k] = e < total ? bj + (int64_t)(e - oj) : -1;
       }
-      const int32_t uj = __shfl(u, j, kWave);
-      const int64_t bj = __shfl(beg, j, kWave);
-      const uint32_t oj = __shfl(off, j, kWave);
-      bool claimed = false;
-      int32_t v = -1;
-      int64_t degv = 0;
-      if (e < total) {
-        v = a.g.col[bj + (int64_t)(e - oj)];
-        claimed = td_claim(a, v, uj, degv);
-        if (STATS) acc.scanned += 1;
-      }
-      wave_append(a, claimed, v, degv, acc);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = ea[k] >= 0 ? a.g.col[ea[k]] : -1;
+      td_claim4<BLOCK, STATS>(a, st, acc, v, u);
     }
   }
-  flush_acc<STATS>(a, acc);
 }
 
 // Bottom-up step: each unvisited vertex scans its neighbours in order and
 // stops at the first one in F_d.  Lane i of a wave owns vertex 64w+i, so the
 // next-frontier and visited words come from one ballot with a single writer
 // (no atomics); words whose 64 vertices are all visited are skipped whole.
-template <bool STATS>
-__device__ void bu_step(const StepArgs &a, int64_t gwave, int64_t nwaves) {
+// The step is bound by load latency (visited word -> row offsets ->
+// neighbours -> frontier bits), so a wave works on J words at once and
+// fetches R neighbours per vertex per round: up to R*J independent
+// neighbour loads and frontier probes are in flight per lane.  The first hit
+// in list order wins.
+#ifndef GAP_BU_WORDS
+#define GAP_BU_WORDS 4
+#endif
+#ifndef GAP_BU_ROUND
+#define GAP_BU_ROUND 4
+#endif
+template <int BLOCK, bool STATS, int J = GAP_BU_WORDS, int R = GAP_BU_ROUND>
+__device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
+                        int64_t nwaves) {
   const int lane = lane_id();
   const int64_t nwords = (a.g.n + kWave - 1) / kWave;
-  LaneAcc acc;
-  for (int64_t w = gwave; w < nwords; w += nwaves) {
-    const uint64_t vis = a.vbm[w];
-    if (vis == ~0ull) {
-      if (lane == 0) a.nbm[w] = 0ull;
-      continue;
-    }
-    const int64_t v = w * kWave + lane;
-    const bool need = ((vis >> lane) & 1ull) == 0ull;
-    bool found = false;
-    int32_t pu = -1;
-    int64_t degv = 0;
-    if (need) {
-      const int64_t beg = a.g.row_ptr[v], end = a.g.row_ptr[v + 1];
-      degv = end - beg;
-      if (STATS) acc.unvisited += 1;
-      for (int64_t e = beg; e < end; ++e) {
-        const int32_t u = a.g.col[e];
-        if (STATS) acc.scanned += 1;
-        if ((a.fbm[u >> 6] >> (u & 63)) & 1ull) {
-          found = true;
-          pu = u;
-          break;
-        }
+  for (int64_t base = gwave * J; base < nwords; base += nwaves * J) {
+    uint64_t vis[J];
+    int64_t e[J], end[J];
+    int32_t pu[J];
+    bool act[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) vis[j] = (base + j < nwords) ? a.vbm[base + j] : ~0ull;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int64_t v = (base + j) * kWave + lane;
+      act[j] = ((vis[j] >> lane) & 1ull) == 0ull;
+      e[j] = 0;
+      end[j] = 0;
+      pu[j] = -1;
+      if (act[j]) {
+        e[j] = a.g.row_ptr[v];
+        end[j] = a.g.row_ptr[v + 1];
+        if (STATS) acc.unvisited += 1;
       }
     }
-    if (found) {
-      a.parent[v] = pu;
-      a.depth[v] = a.d + 1;
+    int64_t degv[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) degv[j] = end[j] - e[j];
+    bool any = true;
+    while (any) {
+      int32_t u[J][R];
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int k = 0; k < R; ++k) u[j][k] = (act[j] && e[j] + k < end[j]) ? a.g.col[e[j] + k] : -1;
+      bool hit[J][R];
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          hit[j][k] = u[j][k] >= 0 && ((a.fbm[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
+      bool more = false;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if (!act[j]) continue;
+        int used = 0;
+#pragma unroll
+        for (int k = R - 1; k >= 0; --k)
+          if (hit[j][k]) pu[j] = u[j][k];
+        if (STATS) {  // entries up to and including the first hit
+          for (int k = 0; k < R && e[j] + k < end[j]; ++k) {
+            ++used;
+            if (hit[j][k]) break;
+          }
+          acc.scanned += used;
+        }
+        e[j] += R;
+        if (pu[j] >= 0 || e[j] >= end[j])
+          act[j] = false;
+        else
+          more = true;
+      }
+      any = __ballot(more) != 0ull;
     }
-    const uint64_t b = __ballot(found);
-    if (lane == 0) {
-      a.nbm[w] = b;
-      if (b) a.vbm[w] = vis | b;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const bool found = pu[j] >= 0;
+      const int64_t v = (base + j) * kWave + lane;
+      if (found) {
+        a.parent[v] = pu[j];
+        a.depth[v] = a.d + 1;
+      }
+      const uint64_t b = __ballot(found);
+      if (base + j < nwords && lane == 0) {
+        a.nbm[base + j] = b;
+        if (b) a.vbm[base + j] = vis[j] | b;
+      }
+      stage_append<BLOCK>(a, st, found, (int32_t)v, degv[j], acc);
     }
-    wave_append(a, found, (int32_t)v, degv, acc);
   }
-  flush_acc<STATS>(a, acc);
 }
 
 // Top-down -> bottom-up: build the frontier bitmap (depth == d) and the
@@ -255,24 +457,23 @@ __device__ inline void init_vertices(const DevGraph &g, int32_t *parent, int32_t
   }
 }
 
-// Source into F_0 plus the level -1 totals (run by one thread).
-__device__ inline void init_source(const DevGraph &g, int32_t source, int32_t hub, int32_t chunk,
-                                   int32_t *q0, int2 *c0, Ctl *ctl) {
+// F_0 = {source} in buffer set 0, segment 0 (one thread).  Returns the
+// totals of F_0 to feed the first level boundary.
+__device__ inline Totals init_source(const DevGraph &g, const Queues &Q, Ctl *ctl, int32_t source,
+                                     int32_t hub, int32_t chunk) {
   const int64_t deg = g.row_ptr[source + 1] - g.row_ptr[source];
-  LevelCounters &c = ctl->cnt[2];
-  c = LevelCounters();
   if (deg > hub) {
     const int64_t nch = (deg + chunk - 1) / chunk;
-    for (int64_t k = 0; k < nch; ++k) c0[k] = make_int2(source, (int)k);
-    c.nc = (unsigned long long)nch;
+    for (int64_t k = 0; k < nch; ++k) Q.c0[k] = make_int2(source, (int)k);
+    st_agent(&ctl->seg[0][0].c, (unsigned long long)nch);
   } else {
-    q0[0] = source;
-    c.nq = 1;
+    Q.q0[0] = source;
+    st_agent(&ctl->seg[0][0].q, 1ull);
   }
-  c.nv = 1;
-  c.mf = (unsigned long long)deg;
-  ctl->cnt[0] = LevelCounters();
-  ctl->cnt[1] = LevelCounters();
+  Totals t = {};
+  t.nv = 1;
+  t.mf = (unsigned long long)deg;
+  return t;
 }
 
 // Final pass (Section 3, BFS): every negative parent becomes -1.

@@ -14,6 +14,12 @@ constexpr int kWave = 64;
 // most negative int32 instead; it can only be reached as the source.
 constexpr int32_t kIsolated = INT32_MIN;
 
+// Workgroups are split into kGroups groups (blockIdx % kGroups).  Same-address
+// device atomics serialise (about 12 ns each on MI355X), so every shared
+// counter is per group: a group's workgroups contend on their own cache line,
+// and queues are segmented per group (each segment can hold n vertices).
+constexpr int kGroups = 16;
+
 struct DevGraph {
   const int64_t *row_ptr;  // int64[n+1]
   const int32_t *col;      // int32[nnz], each row ascending
@@ -21,25 +27,53 @@ struct DevGraph {
   int64_t nnz;
 };
 
-// Totals accumulated by one level (single-source search).
-struct LevelCounters {
-  unsigned long long nq;       // entries appended to the next vertex queue
-  unsigned long long nc;       // chunk items appended to the next chunk queue
-  unsigned long long nv;       // vertices claimed: |F_{d+1}|
-  unsigned long long mf;       // sum of degrees over F_{d+1}
-  unsigned long long scanned;  // adjacency entries read (statistics only)
-  unsigned long long unvisited;// bottom-up vertices still searching (stats)
-  unsigned long long pad[2];
+// Level totals reduced across the grid.
+struct Totals {
+  unsigned long long nv;         // vertices claimed: |F_{d+1}|
+  unsigned long long mf;         // sum of degrees over F_{d+1}
+  unsigned long long scanned;    // adjacency entries read (statistics only)
+  unsigned long long unvisited;  // bottom-up vertices still searching (stats)
 };
 
-// Device-resident control block of one workspace.
+struct alignas(128) GroupSlot {
+  Totals part;          // partial totals of this group for the current level
+  unsigned int arrive;  // barrier arrivals of this group
+  unsigned int pad;
+};
+
+struct alignas(128) GenFlag {
+  unsigned int gen;
+  unsigned int pad;
+};
+
+struct alignas(128) SegCount {
+  unsigned long long q;  // vertices appended to this group's queue segment
+  unsigned long long c;  // hub chunk items appended to this group's segment
+};
+
+// What the grid learns at a level boundary: totals of the new frontier and
+// the size of every queue segment that holds it.
+struct alignas(128) Published {
+  Totals t;
+  unsigned long long q[kGroups];
+  unsigned long long c[kGroups];
+};
+
+// Device-resident control block of one workspace (zeroed before a search).
 struct Ctl {
-  LevelCounters cnt[3];     // ring: level d accumulates into cnt[d % 3]
-  unsigned int bar_count;   // grid barrier arrivals
-  unsigned int bar_gen;     // grid barrier generation
-  int err;                  // GAP_ETIMEOUT when a bounded wait gave up
-  int levels;               // levels run by the last search
-  unsigned long long pad[4];
+  GroupSlot grp[kGroups];
+  GroupSlot top;
+  GenFlag gen[kGroups];
+  SegCount seg[2][kGroups];  // live append counters, per queue buffer set
+  Published pub[2];          // frontier of level d lives in pub[d & 1]
+  int err;                   // GAP_ETIMEOUT / GAP_EINTERNAL
+  int levels;                // levels run by the last search
+  int done;                  // device-driven schedules: search finished
+  int dir;                   // device-driven schedules: direction of next step
+  int level;                 // device-driven schedules: next level
+  int have_bm;               // device-driven schedules: bitmaps are current
+  long long mu;              // device-driven schedules: unexplored edges
+  long long nf_prev;         // device-driven schedules: previous frontier size
 };
 
 struct Params {
@@ -106,24 +140,116 @@ __device__ inline uint64_t rt_clock() { return __builtin_amdgcn_s_memrealtime();
 
 constexpr uint64_t kBarrierTimeoutTicks = 300000000ull;  // ~3 s at 100 MHz
 
-// Grid-wide barrier for a cooperative launch.  Every workgroup of the grid
-// must call it the same number of times.  Bounded: a workgroup that waits
-// longer than the timeout records GAP_ETIMEOUT in ctl->err and returns.
-// Returns false once an error has been recorded.
-__device__ inline bool grid_barrier(Ctl *ctl, unsigned int nblocks) {
+__device__ inline unsigned long long ld_agent(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned int ld_agent(const unsigned int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(unsigned int *p, unsigned int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void add_agent(unsigned long long *p, unsigned long long v) {
+  if (v) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int group_size(int g, unsigned int nblocks) {
+  return (int)(nblocks / kGroups) + ((unsigned)g < nblocks % kGroups ? 1 : 0);
+}
+
+// Publishes group h's queue segment sizes of buffer set `bs` into
+// pub[publish] and clears the live counters (one thread per group).
+__device__ inline void publish_segment(Ctl *ctl, int publish, int bs, int h) {
+  Published &P = ctl->pub[publish];
+  const unsigned long long q = ld_agent(&ctl->seg[bs][h].q);
+  const unsigned long long c = ld_agent(&ctl->seg[bs][h].c);
+  st_agent(&P.q[h], q);
+  st_agent(&P.c[h], c);
+  st_agent(&ctl->seg[bs][h].q, 0ull);
+  st_agent(&ctl->seg[bs][h].c, 0ull);
+}
+
+__device__ inline void publish_totals(Ctl *ctl, int publish, const Totals &t) {
+  Published &P = ctl->pub[publish];
+  st_agent(&P.t.nv, t.nv);
+  st_agent(&P.t.mf, t.mf);
+  st_agent(&P.t.scanned, t.scanned);
+  st_agent(&P.t.unvisited, t.unvisited);
+}
+
+__device__ inline void add_totals(GroupSlot &s, const Totals &t) {
+  add_agent(&s.part.nv, t.nv);
+  add_agent(&s.part.mf, t.mf);
+  add_agent(&s.part.scanned, t.scanned);
+  add_agent(&s.part.unvisited, t.unvisited);
+}
+
+__device__ inline Totals take_totals(GroupSlot &s) {
+  Totals t;
+  t.nv = ld_agent(&s.part.nv);
+  t.mf = ld_agent(&s.part.mf);
+  t.scanned = ld_agent(&s.part.scanned);
+  t.unvisited = ld_agent(&s.part.unvisited);
+  st_agent(&s.part.nv, 0ull);
+  st_agent(&s.part.mf, 0ull);
+  st_agent(&s.part.scanned, 0ull);
+  st_agent(&s.part.unvisited, 0ull);
+  return t;
+}
+
+// Grid-wide barrier with a reduction, for a cooperative launch.  Every
+// workgroup calls it the same number of times, with its partial totals in
+// thread 0.  Arrival is two-level (workgroup -> its group -> top) so that no
+// address sees more than ~nblocks/kGroups atomics (same-address atomics
+// serialise).  The last workgroup of each group folds the group's totals
+// into the top slot and, when `publish` >= 0, publishes its group's queue
+// segment sizes of buffer set `bs`; the last group publishes the totals and
+// releases everyone with one release fence and plain flag stores (a release
+// store per flag would write the L2 back once per flag).
+// Bounded: a workgroup that waits longer than the timeout records
+// GAP_ETIMEOUT in ctl->err.  Returns false once an error has been recorded.
+__device__ inline bool grid_sync(Ctl *ctl, unsigned int nblocks, const Totals &part, int publish,
+                                 int bs) {
   __syncthreads();
   __shared__ int s_ok;
   if (threadIdx.x == 0) {
     int ok = 1;
-    unsigned int gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned int prev =
-        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == nblocks - 1) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const int g = (int)(blockIdx.x % kGroups);
+    const unsigned int gen0 = ld_agent(&ctl->gen[g].gen);
+    GroupSlot &gs = ctl->grp[g];
+    add_totals(gs, part);
+    const unsigned int a =
+        __hip_atomic_fetch_add(&gs.arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    bool released = false;
+    if ((int)a == group_size(g, nblocks) - 1) {
+      // last of the group: fold the group into the top slot
+      const Totals t = take_totals(gs);
+      if (publish >= 0) publish_segment(ctl, publish, bs, g);
+      st_agent(&gs.arrive, 0u);
+      add_totals(ctl->top, t);
+      const int ngroups = nblocks < (unsigned)kGroups ? (int)nblocks : kGroups;
+      const unsigned int b = __hip_atomic_fetch_add(&ctl->top.arrive, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+      if ((int)b == ngroups - 1) {
+        // last overall: publish the totals, clear, release every group
+        const Totals all = take_totals(ctl->top);
+        st_agent(&ctl->top.arrive, 0u);
+        if (publish >= 0) {
+          publish_totals(ctl, publish, all);
+          // groups without workgroups (nblocks < kGroups) publish empty segments
+          for (int h = ngroups; h < kGroups; ++h) publish_segment(ctl, publish, bs, h);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (int h = 0; h < kGroups; ++h) st_agent(&ctl->gen[h].gen, gen0 + 1u);
+        released = true;
+      }
+    }
+    if (!released) {
       const uint64_t t0 = rt_clock();
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (ld_agent(&ctl->gen[g].gen) == gen0) {
         __builtin_amdgcn_s_sleep(1);
         if (rt_clock() - t0 > kBarrierTimeoutTicks) {
           __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
@@ -132,8 +258,8 @@ __device__ inline bool grid_barrier(Ctl *ctl, unsigned int nblocks) {
           break;
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     s_ok = ok;
   }

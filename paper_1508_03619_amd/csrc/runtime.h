@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstddef>
 #include <cstdint>
 #include <mutex>
 #include <vector>
@@ -66,7 +67,11 @@ struct Workspace {
   uint64_t *bm[3] = {nullptr, nullptr, nullptr};  // frontier A, frontier B, visited
   int32_t *depth_scratch = nullptr;
   Ctl *ctl = nullptr;
-  LevelCounters *h_cnt = nullptr;  // pinned readback
+  int *h_flags = nullptr;  // pinned readback of err, levels, done
+  void *dd_args = nullptr; // device copy of the per-search arguments
+  void *h_args = nullptr;  // pinned staging of the same
+  void *graph_exec = nullptr;  // captured level graph (hipGraphExec_t)
+  int graph_key = 0, graph_grid = 0;
   DevLevelRec *recs = nullptr;
   int32_t cap_recs = 0;
   // multi-source
@@ -80,6 +85,17 @@ Workspace *workspace_for(int dev, hipStream_t stream);
 gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const gap_params &p);
 gap_status workspace_reserve_recs(Workspace *ws, int32_t nrec);
 gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes);
+
+// Persistent kernels need every workgroup resident at once.  Two of them
+// started on different streams could each get part of the machine and wait
+// on each other, so launches of persistent kernels are ordered across
+// streams: the new stream waits on an event recorded after the previous
+// persistent launch.  Hold the returned lock from begin to end.
+struct CoopOrder {
+  std::unique_lock<std::mutex> lock;
+};
+gap_status coop_begin(int dev, hipStream_t s, CoopOrder *o);
+gap_status coop_end(int dev, hipStream_t s, CoopOrder *o);
 
 gap_params params_current();
 gap_status params_check(const gap_params &p);

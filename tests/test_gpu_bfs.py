@@ -11,10 +11,7 @@ from tests.gpuutil import assert_valid, device_bfs, graph_pair, say
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [
-    dict(mode=0, direction=0), dict(mode=0, direction=1), dict(mode=0, direction=2),
-    dict(mode=1, direction=0), dict(mode=1, direction=1), dict(mode=1, direction=2),
-]
+SCHEDULES = [dict(mode=m, direction=d) for m in (0, 1, 2) for d in (0, 1, 2)]
 
 
 def small_cases():
@@ -129,7 +126,7 @@ def test_hub_splitting_and_tuning_invariance(gpu):
     for src in srcs:
         ref = A.bfs(src)[0]
         for st in settings:
-            for mode in (0, 1):
+            for mode in (0, 1, 2):
                 say(f"tuning src={src} {st} mode={mode}")
                 parent, depth = device_bfs(gpu, g, src, params=dict(st, mode=mode))
                 assert_valid(A, src, parent, depth, ref, what=str(st))
@@ -187,7 +184,7 @@ def test_grid_road_like(gpu):
     el = inputs.grid(300, 200, seed=7)
     g, A = graph_pair(gpu, el.n, el.src, el.dst)
     for src in inputs.pick_sources(el, 3, seed=8):
-        for mode in (0, 1):
+        for mode in (0, 1, 2):
             say(f"grid300x200 src={src} mode={mode}")
             parent, depth = device_bfs(gpu, g, int(src), params=dict(mode=mode))
             assert_valid(A, int(src), parent, depth, what="grid")
@@ -201,7 +198,7 @@ def test_stats_records(gpu):
     import torch
     dref = A.bfs(src)[0]
     deg = np.diff(A.offsets)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
         depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
         recs = gpu.bfs(g, src, parent, depth, params=dict(mode=mode), stats=True)
