@@ -20,7 +20,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -38,13 +37,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1508_03619_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
+PROFILE_COPY_BYTES = 1 << 30
 
 
 def algorithmic_bytes(recs, n) -> int:
@@ -96,6 +89,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", default="rmat22,urand22")
+    ap.add_argument("--profile-leg", action="store_true",
+                    help="for rocprofv3 counter runs: a copy of known size, then one search per "
+                         "source, no timing and no JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -117,6 +113,19 @@ def main():
     for name in args.graphs.split(","):
         el = inputs.workload(name)
         cases.append(GraphCase(name, el, gb, torch, args.sources, inputs.SOURCE_SEEDS[name]))
+
+    if args.profile_leg:
+        a = torch.empty(PROFILE_COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            gb.stream_copy(b, a, PROFILE_COPY_BYTES)
+        torch.cuda.synchronize()
+        for c in cases:
+            for s in c.sources:
+                gb.bfs(c.g, int(s), c.parent, c.depth)
+        torch.cuda.synchronize()
+        log("profile leg done")
+        return
 
     # Per-source component edge counts m_s and per-level records (untimed).
     for c in cases:
@@ -190,12 +199,13 @@ def main():
 
     # HBM traffic from committed rocprofv3 counter runs, if they match this build.
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_k_bfs_persistent_rmat22_urand22.json")
+    tpath = os.path.join(ROOT, "profiles", "traffic_k_bfs_persistent_rmat22_urand22.txt")
     if os.path.exists(tpath):
+        from paper_1508_03619_amd.rocprof_summary import kernel_source_hash
         try:
             tj = json.load(open(tpath))
             if tj.get("source_hash") == kernel_source_hash():
-                traffic = tj.get("bytes_per_launch")
+                traffic = int(tj.get("bytes_per_launch"))
         except Exception:
             traffic = None
 
