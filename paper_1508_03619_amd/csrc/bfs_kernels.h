@@ -67,81 +67,94 @@ __device__ inline int seg_of(unsigned long long i, const unsigned long long *pre
   return h;
 }
 
-// Append this wave's newly reached vertices to F_{d+1}: degree <= hub ->
-// vertex queue, larger -> ceil(deg/chunk) chunk items so that one hub is
-// expanded by many waves.
+// Appends the vertices with `want` set to this workgroup's staged vertex
+// queue (one LDS atomic per wave; overflow goes to the group's segment).
 template <int BLOCK>
-__device__ inline void stage_append(const StepArgs &a, Stage<BLOCK> &st, bool claimed, int32_t v,
-                                    int64_t degv, LaneAcc &acc) {
-  const uint64_t any = __ballot(claimed);
-  if (any == 0) return;
+__device__ inline void stage_vertices(const StepArgs &a, Stage<BLOCK> &st, bool want, int32_t v) {
+  const uint64_t ms = __ballot(want);
+  if (!ms) return;
   const int lane = lane_id();
   const int g = (int)(blockIdx.x % kGroups);
   const int bs_out = a.bs_in ^ 1;
-  const bool big = claimed && degv > a.hub;
-  const bool small = claimed && !big;
-  const uint64_t ms = __ballot(small);
-  if (ms) {
-    const int leader = first_lane(ms);
-    const unsigned int cnt = (unsigned int)__popcll(ms);
-    unsigned int base = 0;
-    if (lane == leader) base = atomicAdd(&st.qn, cnt);
-    base = __shfl(base, leader, kWave);
-    const unsigned int cap = Stage<BLOCK>::QCAP;
-    const unsigned int ov_start = base > cap ? base : cap;
-    const unsigned int n_ov = base + cnt > cap ? base + cnt - ov_start : 0u;
-    unsigned long long gbase = 0;
-    if (n_ov) {
-      if (lane == leader) gbase = atomicAdd(&a.ctl->seg[bs_out][g].q, (unsigned long long)n_ov);
-      gbase = __shfl(gbase, leader, kWave);
-    }
-    if (small) {
-      const unsigned int slot = base + lane_rank(ms);
-      if (slot < cap)
-        st.q[slot] = v;
-      else
-        a.Q.qs(bs_out)[g * a.Q.n + (int64_t)(gbase + (slot - ov_start))] = v;
-    }
+  const int leader = first_lane(ms);
+  const unsigned int cnt = (unsigned int)__popcll(ms);
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(&st.qn, cnt);
+  base = __shfl(base, leader, kWave);
+  const unsigned int cap = Stage<BLOCK>::QCAP;
+  const unsigned int ov_start = base > cap ? base : cap;
+  const unsigned int n_ov = base + cnt > cap ? base + cnt - ov_start : 0u;
+  unsigned long long gbase = 0;
+  if (n_ov) {
+    if (lane == leader) gbase = atomicAdd(&a.ctl->seg[bs_out][g].q, (unsigned long long)n_ov);
+    gbase = __shfl(gbase, leader, kWave);
   }
-  const uint64_t mb = __ballot(big);
-  if (mb) {
-    // hubs: ceil(deg/chunk) items each, written by the whole wave (item i
-    // belongs to the lane whose prefix range holds i) so no lane loops alone
-    const uint32_t nch = big ? (uint32_t)((degv + a.chunk - 1) / a.chunk) : 0u;
-    uint32_t total;
-    const uint32_t off = wave_excl_scan_u32(nch, total);
-    const int leader = first_lane(mb);
-    unsigned int base = 0;
-    if (lane == leader) base = atomicAdd(&st.cn, total);
-    base = __shfl(base, leader, kWave);
-    const unsigned int cap = Stage<BLOCK>::CCAP;
-    const unsigned int ov_start = base > cap ? base : cap;
-    const unsigned int n_ov = base + total > cap ? base + total - ov_start : 0u;
-    unsigned long long gbase = 0;
-    if (n_ov) {
-      if (lane == leader) gbase = atomicAdd(&a.ctl->seg[bs_out][g].c, (unsigned long long)n_ov);
-      gbase = __shfl(gbase, leader, kWave);
-    }
-    for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
-      const uint32_t i = i0 + (uint32_t)lane;
-      int j = 0;
+  if (want) {
+    const unsigned int slot = base + lane_rank(ms);
+    if (slot < cap)
+      st.q[slot] = v;
+    else
+      a.Q.qs(bs_out)[g * a.Q.n + (int64_t)(gbase + (slot - ov_start))] = v;
+  }
+}
+
+// Appends ceil(deg/chunk) chunk items {v, k | flag} for every lane with
+// `want` set.  The whole wave writes them (item i belongs to the lane whose
+// prefix range holds i), so a hub never leaves one lane looping alone.
+template <int BLOCK>
+__device__ inline void stage_chunks(const StepArgs &a, Stage<BLOCK> &st, bool want, int32_t v,
+                                    int64_t degv, int flag) {
+  const uint64_t mb = __ballot(want);
+  if (!mb) return;
+  const int lane = lane_id();
+  const int g = (int)(blockIdx.x % kGroups);
+  const int bs_out = a.bs_in ^ 1;
+  const uint32_t nch = want ? (uint32_t)((degv + a.chunk - 1) / a.chunk) : 0u;
+  uint32_t total;
+  const uint32_t off = wave_excl_scan_u32(nch, total);
+  const int leader = first_lane(mb);
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(&st.cn, total);
+  base = __shfl(base, leader, kWave);
+  const unsigned int cap = Stage<BLOCK>::CCAP;
+  const unsigned int ov_start = base > cap ? base : cap;
+  const unsigned int n_ov = base + total > cap ? base + total - ov_start : 0u;
+  unsigned long long gbase = 0;
+  if (n_ov) {
+    if (lane == leader) gbase = atomicAdd(&a.ctl->seg[bs_out][g].c, (unsigned long long)n_ov);
+    gbase = __shfl(gbase, leader, kWave);
+  }
+  for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+    const uint32_t i = i0 + (uint32_t)lane;
+    int j = 0;
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const uint32_t oc = __shfl(off, j + step, kWave);
-        if (oc <= i) j += step;  // largest j with off_j <= i owns item i
-      }
-      const int32_t vj = __shfl(v, j, kWave);
-      const uint32_t oj = __shfl(off, j, kWave);
-      if (i < total) {
-        const unsigned int slot = base + i;
-        const int2 item = make_int2(vj, (int)(i - oj));
-        if (slot < cap)
-          st.c[slot] = item;
-        else
-          a.Q.cs(bs_out)[g * a.Q.ccap + (int64_t)(gbase + (slot - ov_start))] = item;
-      }
+    for (int step = 32; step >= 1; step >>= 1) {
+      const uint32_t oc = __shfl(off, j + step, kWave);
+      if (oc <= i) j += step;  // largest j with off_j <= i owns item i
+    }
+    const int32_t vj = __shfl(v, j, kWave);
+    const uint32_t oj = __shfl(off, j, kWave);
+    if (i < total) {
+      const unsigned int slot = base + i;
+      const int2 item = make_int2(vj, (int)(i - oj) | flag);
+      if (slot < cap)
+        st.c[slot] = item;
+      else
+        a.Q.cs(bs_out)[g * a.Q.ccap + (int64_t)(gbase + (slot - ov_start))] = item;
     }
   }
+}
+
+// Appends this wave's newly reached vertices to F_{d+1}: degree <= hub ->
+// vertex queue, larger -> chunk items so that one hub is expanded by many
+// waves; accumulates the frontier totals.
+template <int BLOCK>
+__device__ inline void stage_append(const StepArgs &a, Stage<BLOCK> &st, bool claimed, int32_t v,
+                                    int64_t degv, LaneAcc &acc) {
+  if (__ballot(claimed) == 0ull) return;
+  const bool big = claimed && degv > a.hub;
+  stage_vertices<BLOCK>(a, st, claimed && !big, v);
+  stage_chunks<BLOCK>(a, st, big, v, degv, 0);
   if (claimed) {
     acc.mf += (unsigned long long)degv;
     acc.nv += 1;
