@@ -165,8 +165,10 @@ typedef struct gap_params {
                             into chunk work items */
   int32_t chunk_edges;   /* edges per chunk work item (multiple of 64) */
   int32_t graph_chunk;   /* GAP_MODE_GRAPH: levels per captured graph */
-  int32_t batch_mode;    /* multi-source: 0 persistent, 1 per-level */
-  int32_t reserved[6];
+  int32_t batch_mode;    /* multi-source schedule: 0 = persistent kernel */
+  int32_t batch_alpha;   /* multi-source: top-down -> bottom-up threshold */
+  int32_t batch_beta;    /* multi-source: bottom-up -> top-down threshold */
+  int32_t reserved[4];
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

@@ -106,6 +106,8 @@ static gap_params default_params() {
   p.chunk_edges = 256;
   p.graph_chunk = 16;
   p.batch_mode = 0;
+  p.batch_alpha = 8;
+  p.batch_beta = 18;
   return p;
 }
 
@@ -149,8 +151,12 @@ gap_status params_check(const gap_params &p) {
     set_error("params: graph_chunk must be in [1, 4096]");
     return GAP_EINVAL;
   }
-  if (p.batch_mode < 0 || p.batch_mode > 1) {
-    set_error("params: batch_mode must be 0 or 1");
+  if (p.batch_mode != 0) {
+    set_error("params: batch_mode must be 0 (persistent kernel)");
+    return GAP_EINVAL;
+  }
+  if (p.batch_alpha < 1 || p.batch_beta < 1) {
+    set_error("params: batch_alpha and batch_beta must be >= 1");
     return GAP_EINVAL;
   }
   return GAP_OK;

@@ -732,7 +732,9 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
   a.Q.n = nvirt;
   a.Q.ccap = chunk_cap;
   a.ctl = reinterpret_cast<MsCtl *>(base + o_ctl);
-  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges};
+  // bottom-up cannot stop early while any lane still misses a vertex, so the
+  // batch has its own switching thresholds
+  a.p = Params{p.batch_alpha, p.batch_beta, p.direction, p.hub_degree, p.chunk_edges};
   const int64_t *d_tile_base = reinterpret_cast<const int64_t *>(base + o_tb);
 
   CoopOrder order;

@@ -36,7 +36,8 @@ class _Params(ctypes.Structure):
                 ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("hub_degree", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
                 ("graph_chunk", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("batch_alpha", ctypes.c_int32), ("batch_beta", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_ if f[0] != "reserved"]
