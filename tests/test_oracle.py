@@ -238,38 +238,43 @@ def test_adjacency_matches_scipy_rmat(oracle_lib):
 
 # ---- 6. validator sensitivity: planted mistakes are rejected -------------
 
-def test_validator_rejects_planted_mistakes(oracle_lib):
+def validator_ok(L):
+    """True when the validator rejects every planted mistake with the right code."""
     n, s, d, dist = sg.disjoint_union(sg.full_grid(6, 5), sg.cycle(5), sg.path(1))
-    A = _adj(n, s, d, oracle_lib)
+    # a diagonal 7-14 closes the triangle 7-8-14, so 8 and 14 are neighbours
+    # on the same level when the search starts at 7
+    s = np.append(s, np.int32(7)).astype(np.int32)
+    d = np.append(d, np.int32(14)).astype(np.int32)
+    A = _adj(n, s, d, L)
     src = 7
     depth, parent = A.bfs(src)
-    assert A.check(src, depth, parent, depth) == (0, -1)
+    if A.check(src, depth, parent, depth) != (0, -1):
+        return False
     far = int(np.argmax(depth))          # a reached vertex at the largest depth
     unreached = int(np.flatnonzero(depth < 0)[0])
-
-    p = parent.copy(); p[src] = -1
-    assert A.check(src, depth, p)[0] == 2
-    p = parent.copy(); p[unreached] = 0
-    assert A.check(src, depth, p)[0] == 3
-    p = parent.copy(); p[far] = -1
-    assert A.check(src, depth, p)[0] == 3
-    p = parent.copy(); p[far] = -5       # leaked negative encoding
-    assert A.check(src, depth, p)[0] == 3
-    p = parent.copy(); p[far] = n + 3    # out of range
-    assert A.check(src, depth, p)[0] == 4
-    # a reached vertex with a same-level-minus-one vertex that is not its neighbour
     tgt, nonadj = next((v, u) for v in range(30) for u in range(30)
                        if depth[v] >= 2 and depth[u] == depth[v] - 1
                        and u not in A.adj[A.offsets[v]:A.offsets[v + 1]])
-    p = parent.copy(); p[tgt] = nonadj   # right level, not a neighbour
-    assert A.check(src, depth, p)[0] == 4
-    same = [int(v) for v in A.adj[A.offsets[far]:A.offsets[far + 1]] if depth[v] == depth[far]]
-    deeper = [int(v) for v in A.adj[A.offsets[far]:A.offsets[far + 1]] if depth[v] != depth[far] - 1]
-    if same or deeper:
-        p = parent.copy(); p[far] = (same or deeper)[0]  # neighbour, wrong level
-        assert A.check(src, depth, p)[0] == 5
-    dd = depth.copy(); dd[far] += 1
-    assert A.check(src, depth, parent, dd)[0] == 1
+    deep_v, deep_u = next((v, int(u)) for v in range(30) for u in A.adj[A.offsets[v]:A.offsets[v + 1]]
+                          if depth[v] >= 1 and depth[u] == depth[v] + 1)
+    planted = []
+    p = parent.copy(); p[14] = 8; planted.append((p, None, 5))          # neighbour, same level
+    p = parent.copy(); p[deep_v] = deep_u; planted.append((p, None, 5))  # neighbour, one level down
+    p = parent.copy(); p[src] = -1; planted.append((p, None, 2))
+    p = parent.copy(); p[unreached] = 0; planted.append((p, None, 3))
+    p = parent.copy(); p[far] = -1; planted.append((p, None, 3))
+    p = parent.copy(); p[far] = -5; planted.append((p, None, 3))      # leaked negative encoding
+    p = parent.copy(); p[far] = n + 3; planted.append((p, None, 4))   # out of range
+    p = parent.copy(); p[tgt] = nonadj; planted.append((p, None, 4))  # right level, not a neighbour
+    dd = depth.copy(); dd[far] += 1; planted.append((parent, dd, 1))
+    for p, dtest, code in planted:
+        if A.check(src, depth, p, dtest)[0] != code:
+            return False
+    return True
+
+
+def test_validator_rejects_planted_mistakes(oracle_lib):
+    assert validator_ok(oracle_lib)
 
 
 def test_validator_accepts_any_valid_parent(oracle_lib):

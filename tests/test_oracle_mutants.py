@@ -1,0 +1,64 @@
+"""The oracle's pins must catch plausible mistakes in the oracle.
+
+Each case copies oracle/oracle.c, plants one mistake (a textual edit, on the
+CPU), compiles the copy to a temporary library and runs the pin functions of
+test_oracle.py against it: at least one pin must fail.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle as T
+
+MUTANTS = {
+    "depth_plus_two": ("depth[v] = depth[u] + 1;", "depth[v] = depth[u] + 2;"),
+    "lifo_queue": ("int32_t u = queue[head++];", "int32_t u = queue[--tail];"),
+    "parent_is_self": ("        parent[v] = u;\n", "        parent[v] = (int32_t)v;\n"),
+    "no_reverse_edge": ("    offsets[v + 1] += 1;\n", "\n"),
+    "no_dedup": ("      if (i > start && adj[i] == adj[i - 1]) continue;\n", "\n"),
+    "keeps_self_loops": ("    if (u == v) continue;\n    offsets[u + 1] += 1;",
+                         "    offsets[u + 1] += 1;"),
+    "validator_weak_level": ("if (depth_ref[p] != depth_ref[v] - 1) {",
+                             "if (depth_ref[p] > depth_ref[v]) {"),
+    "validator_no_edge_check": ("return lo < offsets[a + 1] && adj[lo] == b;", "return 1;"),
+    "unionfind_no_union": ("        label[rb] = ra;", "        label[rb] = rb;"),
+}
+
+
+def pins_pass(L):
+    from paper_1508_03619_amd import inputs
+    if not T.exhaustive_depths_ok(L, 4):
+        return False
+    if not all(T.random_graph_ok(L, seed) for seed in range(12)):
+        return False
+    if not T.closed_forms_ok(L) or not T.golden_ok(L):
+        return False
+    el = inputs.rmat(10, 8, seed=3)
+    if not T.invariants_ok(L, el, inputs.pick_sources(el, 3, seed=4)):
+        return False
+    return T.validator_ok(L)
+
+
+def test_unmutated_oracle_passes_the_pins(oracle_lib):
+    assert pins_pass(oracle_lib)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
+    assert src.count(old) >= 1, f"mutation anchor missing for {name}"
+    mutated = src.replace(old, new, 1)
+    csrc = tmp_path / "oracle_mut.c"
+    csrc.write_text(mutated)
+    so = str(tmp_path / "liboracle_mut.so")
+    import subprocess
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-std=c11", "-o", so, str(csrc)], check=True)
+    L = oracle._bind(so)
+    try:
+        caught = not pins_pass(L)
+    except Exception:
+        caught = True  # a crash-free exception (e.g. bad input detected) also counts
+    assert caught, f"mutant {name} passed every pin"
