@@ -168,7 +168,10 @@ typedef struct gap_params {
   int32_t batch_mode;    /* multi-source schedule: 0 = persistent kernel */
   int32_t batch_alpha;   /* multi-source: top-down -> bottom-up threshold */
   int32_t batch_beta;    /* multi-source: bottom-up -> top-down threshold */
-  int32_t reserved[4];
+  int32_t grid_split;    /* k >= 1: a persistent launch takes 1/k of the CUs
+                            and at most k of them run at once (so searches
+                            queued on different streams can overlap) */
+  int32_t reserved[3];
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

@@ -6,6 +6,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "runtime.h"
 
@@ -49,6 +50,11 @@ gap_status device_info(int dev, const DeviceInfo **out) {
     di.clock_khz = prop.clockRate;
     di.total_mem = prop.totalGlobalMem;
     di.coop_supported = prop.cooperativeLaunch;
+    int xccs = 1;
+    if (hipDeviceGetAttribute(&xccs, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || xccs < 1)
+      xccs = 1;
+    (void)hipGetLastError();
+    di.xccs = xccs;
     snprintf(di.arch, sizeof(di.arch), "%s", prop.gcnArchName);
     it = g_dev.emplace(dev, di).first;
   }
@@ -60,9 +66,10 @@ gap_status device_info(int dev, const DeviceInfo **out) {
 
 struct CoopState {
   std::mutex mu;
-  hipEvent_t ev = nullptr;
-  bool recorded = false;
-  hipStream_t last = nullptr;
+  std::vector<hipEvent_t> ev;      // ring of k events
+  std::vector<bool> recorded;
+  int k = 0;
+  unsigned long long next = 0;     // launches ordered so far
 };
 static std::map<int, std::unique_ptr<CoopState>> g_coop;
 
@@ -73,21 +80,49 @@ static CoopState *coop_state(int dev) {
   return p.get();
 }
 
-gap_status coop_begin(int dev, hipStream_t s, CoopOrder *o) {
+gap_status coop_begin(int dev, hipStream_t s, int k, CoopOrder *o) {
   CoopState *cs = coop_state(dev);
   o->lock = std::unique_lock<std::mutex>(cs->mu);
-  if (!cs->ev) GAP_HIP(hipEventCreateWithFlags(&cs->ev, hipEventDisableTiming));
-  if (cs->recorded && cs->last != s) GAP_HIP(hipStreamWaitEvent(s, cs->ev, 0));
+  if (k < 1) k = 1;
+  if (cs->k != k) {
+    // a new ring size: the first launch waits for every launch of the old ring
+    for (size_t i = 0; i < cs->ev.size(); ++i)
+      if (cs->recorded[i]) GAP_HIP(hipStreamWaitEvent(s, cs->ev[i], 0));
+    for (hipEvent_t e : cs->ev) (void)hipEventDestroy(e);
+    cs->ev.assign((size_t)k, nullptr);
+    cs->recorded.assign((size_t)k, false);
+    for (auto &e : cs->ev) GAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    cs->k = k;
+    cs->next = 0;
+  }
+  o->slot = (int)(cs->next % (unsigned long long)k);
+  if (cs->recorded[(size_t)o->slot]) GAP_HIP(hipStreamWaitEvent(s, cs->ev[(size_t)o->slot], 0));
   return GAP_OK;
 }
 
 gap_status coop_end(int dev, hipStream_t s, CoopOrder *o) {
   CoopState *cs = coop_state(dev);
-  hipError_t e = hipEventRecord(cs->ev, s);
-  cs->recorded = (e == hipSuccess);
-  cs->last = s;
+  hipError_t e = hipEventRecord(cs->ev[(size_t)o->slot], s);
+  cs->recorded[(size_t)o->slot] = (e == hipSuccess);
+  cs->next += 1;
   o->lock.unlock();
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return GAP_OK;
+}
+
+gap_status launch_resident(const void *kern, int max_grid, int block, void **kargs, int split,
+                           const DeviceInfo *di, hipStream_t s, int *grid_out) {
+  int grid = max_grid;
+  if (split > 1) {
+    const int x = di->xccs;
+    grid = max_grid / split / x * x;
+    if (grid < x) grid = max_grid / split;
+    if (grid < 1) grid = 1;
+    GAP_HIP(hipLaunchKernel(kern, dim3(grid), dim3(block), kargs, 0, s));
+  } else {
+    GAP_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), kargs, 0, s));
+  }
+  if (grid_out) *grid_out = grid;
   return GAP_OK;
 }
 
@@ -108,6 +143,7 @@ static gap_params default_params() {
   p.batch_mode = 0;
   p.batch_alpha = 8;
   p.batch_beta = 18;
+  p.grid_split = 1;
   return p;
 }
 
@@ -153,6 +189,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.batch_mode != 0) {
     set_error("params: batch_mode must be 0 (persistent kernel)");
+    return GAP_EINVAL;
+  }
+  if (p.grid_split < 1 || p.grid_split > 64) {
+    set_error("params: grid_split must be in [1, 64]");
     return GAP_EINVAL;
   }
   if (p.batch_alpha < 1 || p.batch_beta < 1) {

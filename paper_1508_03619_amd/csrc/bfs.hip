@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kLevelBlock) void k_dd_fixup(DDArgs *A) {
 
 template <int BLOCK, bool STATS>
 static gap_status launch_persistent(const SearchArgs &a, const DeviceInfo *di, int blocks_per_cu,
-                                    hipStream_t stream) {
+                                    int split, hipStream_t stream) {
   auto kern = k_bfs_persistent<BLOCK, STATS>;
   int per_cu = 0;
   GAP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
@@ -237,21 +237,19 @@ static gap_status launch_persistent(const SearchArgs &a, const DeviceInfo *di, i
     return GAP_EDEVICE;
   }
   if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
-  const int grid = per_cu * di->cus;
   SearchArgs args = a;
   void *kargs[] = {&args};
-  GAP_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(BLOCK), kargs, 0,
-                                     stream));
-  return GAP_OK;
+  return launch_resident((const void *)kern, per_cu * di->cus, BLOCK, kargs, split, di, stream,
+                         nullptr);
 }
 
 template <bool STATS>
 static gap_status dispatch_persistent(const SearchArgs &a, const DeviceInfo *di,
                                       const gap_params &p, hipStream_t stream) {
   switch (p.block) {
-    case 256: return launch_persistent<256, STATS>(a, di, p.blocks_per_cu, stream);
-    case 512: return launch_persistent<512, STATS>(a, di, p.blocks_per_cu, stream);
-    default: return launch_persistent<1024, STATS>(a, di, p.blocks_per_cu, stream);
+    case 256: return launch_persistent<256, STATS>(a, di, p.blocks_per_cu, p.grid_split, stream);
+    case 512: return launch_persistent<512, STATS>(a, di, p.blocks_per_cu, p.grid_split, stream);
+    default: return launch_persistent<1024, STATS>(a, di, p.blocks_per_cu, p.grid_split, stream);
   }
 }
 
@@ -416,7 +414,7 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
   } else {
     GAP_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), stream));
     CoopOrder order;
-    st = coop_begin(g->device, stream, &order);
+    st = coop_begin(g->device, stream, p.grid_split, &order);
     if (st != GAP_OK) return st;
     st = want_stats ? dispatch_persistent<true>(a, di, p, stream)
                     : dispatch_persistent<false>(a, di, p, stream);

@@ -582,7 +582,7 @@ __global__ __launch_bounds__(kOutBlock) void k_ms_output(MsArgs a, int64_t nword
 // ---- host side ------------------------------------------------------------------------
 
 template <int W>
-static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int64_t ntiles,
+static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int split, int64_t ntiles,
                             const int64_t *tile_base, hipStream_t stream) {
   auto kern = k_msbfs<W>;
   int per_cu = 0;
@@ -591,11 +591,12 @@ static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int64_t ntile
     set_error("multi-source kernel does not fit on a compute unit");
     return GAP_EDEVICE;
   }
-  const int grid = di->cus;  // one 1024-thread workgroup per CU
   MsArgs args = a;
   void *kargs[] = {&args};
-  GAP_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(kMsBlock), kargs, 0,
-                                     stream));
+  // 1024-thread workgroups, one per CU
+  gap_status st = launch_resident((const void *)kern, di->cus, kMsBlock, kargs, split, di, stream,
+                                  nullptr);
+  if (st != GAP_OK) return st;
   int64_t blocks = (ntiles + kOutBlock / kWave - 1) / (kOutBlock / kWave);
   if (blocks > (int64_t)di->cus * 8) blocks = (int64_t)di->cus * 8;
   if (blocks < 1) blocks = 1;
@@ -738,12 +739,12 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
   const int64_t *d_tile_base = reinterpret_cast<const int64_t *>(base + o_tb);
 
   CoopOrder order;
-  st = coop_begin(dev, stream, &order);
+  st = coop_begin(dev, stream, p.grid_split, &order);
   if (st != GAP_OK) return st;
   switch (W) {
-    case 1: st = launch_ms<1>(a, di, ntiles, d_tile_base, stream); break;
-    case 2: st = launch_ms<2>(a, di, ntiles, d_tile_base, stream); break;
-    default: st = launch_ms<4>(a, di, ntiles, d_tile_base, stream); break;
+    case 1: st = launch_ms<1>(a, di, p.grid_split, ntiles, d_tile_base, stream); break;
+    case 2: st = launch_ms<2>(a, di, p.grid_split, ntiles, d_tile_base, stream); break;
+    default: st = launch_ms<4>(a, di, p.grid_split, ntiles, d_tile_base, stream); break;
   }
   gap_status st2 = coop_end(dev, stream, &order);
   if (st != GAP_OK) return st;

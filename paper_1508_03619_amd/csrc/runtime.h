@@ -43,6 +43,7 @@ struct DeviceInfo {
   size_t total_mem = 0;
   char arch[64] = {0};
   int coop_supported = 0;
+  int xccs = 1;  // accelerator complex dies; workgroups are dealt to them in turn
 };
 
 gap_status device_info(int dev, const DeviceInfo **out);
@@ -88,14 +89,29 @@ gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes);
 
 // Persistent kernels need every workgroup resident at once.  Two of them
 // started on different streams could each get part of the machine and wait
-// on each other, so launches of persistent kernels are ordered across
-// streams: the new stream waits on an event recorded after the previous
-// persistent launch.  Hold the returned lock from begin to end.
+// on each other.  With grid_split = k every persistent grid uses at most
+// 1/k of the CUs and at most k persistent launches are in flight on the
+// device: launch i waits (on the device) for an event recorded after launch
+// i-k.  k = 1 orders all persistent launches.  Hold the order from begin to
+// end.
 struct CoopOrder {
   std::unique_lock<std::mutex> lock;
+  int slot = 0;
 };
-gap_status coop_begin(int dev, hipStream_t s, CoopOrder *o);
+gap_status coop_begin(int dev, hipStream_t s, int k, CoopOrder *o);
 gap_status coop_end(int dev, hipStream_t s, CoopOrder *o);
+
+// Launches a kernel whose workgroups wait on each other (grid barriers).
+// max_grid is the largest grid that is resident at once on the whole
+// device.  split = 1: a cooperative launch of max_grid workgroups (the
+// runtime checks residency; cooperative launches do not run concurrently).
+// split = k > 1: an ordinary launch of max_grid / k workgroups rounded down
+// to a multiple of the die count, so each die receives the same number;
+// with at most k such grids in flight (coop_begin) their sum fits on every
+// die at once.  Waits inside the kernels are bounded, so a broken residency
+// assumption ends in GAP_ETIMEOUT rather than a hang.
+gap_status launch_resident(const void *kern, int max_grid, int block, void **kargs, int split,
+                           const DeviceInfo *di, hipStream_t s, int *grid_out);
 
 gap_params params_current();
 gap_status params_check(const gap_params &p);

@@ -1,0 +1,412 @@
+"""Query serving over a pool of device-resident graphs.
+
+A query is one breadth-first search (graph, source) with the output of
+Section 2.1 (parent and depth arrays).  The server keeps every graph of the
+pool resident in HBM (built once, untimed, as Section 2.3 prescribes for the
+graph), admits queries against a device-memory budget, groups queries of the
+same graph into multi-source launches (``gap_bfs_batch``) and keeps several
+launches in flight on separate HIP streams (``grid_split``: each persistent
+launch takes a 1/k share of the compute units, k launches run at once).
+While launches run, newly arrived queries are grouped into the next launch
+of a free stream, so no query waits for a batch it did not join.
+
+The host logic (``Scheduler``, ``serve``) is independent of the device: the
+``GpuExecutor`` runs batches through the library, a ``SimExecutor`` runs the
+same loop on a simulated clock for host-only tests.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# memory accounting
+
+# Device memory one multi-source launch uses per segment of 64*W lanes of a
+# graph with n vertices: visit/frontier/next bitsets (3 * 8W bytes per
+# vertex, rounded to 64-vertex words), per-lane parent/depth staging
+# (8 bytes per lane slot), two vertex queues of 16 segments each.
+# Mirrors the workspace layout of the multi-source kernel.
+def batch_workspace_bytes(n: int, lanes: int) -> int:
+    W = 1 if lanes <= 64 else (2 if lanes <= 128 else 4)
+    segs = -(-lanes // (64 * W))
+    nv = -(-n // 64) * 64
+    per_seg = 3 * 8 * W * nv + 8 * 64 * W * nv + 2 * 4 * 16 * nv
+    return segs * per_seg
+
+
+def query_output_bytes(n: int) -> int:
+    """Parent and depth arrays of one query (int32 each)."""
+    return 8 * n
+
+
+@dataclass
+class Query:
+    qid: int
+    graph: int
+    source: int
+    arrival: float          # seconds, on the server clock
+    start: float = math.nan  # launch time
+    done: float = math.nan   # completion observed by the host
+    batch_size: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class AdmissionError(ValueError):
+    pass
+
+
+class Scheduler:
+    """FIFO admission against a memory budget, same-graph batching.
+
+    ``submit`` queues a query.  ``take_batch`` forms the next launch: the
+    graph of the oldest waiting query, and up to ``max_lanes`` of that
+    graph's waiting queries in arrival order, as many as the budget admits.
+    The oldest query is never overtaken: when its outputs do not fit, no
+    batch is formed until earlier launches release memory.
+    """
+
+    def __init__(self, graph_sizes: Sequence[int], budget_bytes: int, max_lanes: int = 64):
+        if max_lanes < 1:
+            raise ValueError("max_lanes must be >= 1")
+        self.sizes = [int(n) for n in graph_sizes]
+        self.budget = int(budget_bytes)
+        self.max_lanes = int(max_lanes)
+        self.used = 0
+        self.peak_used = 0
+        self._order: collections.deque = collections.deque()   # qids in arrival order
+        self._by_graph: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
+        self._live: Dict[int, Query] = {}                       # waiting queries
+
+    def cost(self, q: Query) -> int:
+        return query_output_bytes(self.sizes[q.graph])
+
+    @property
+    def pending(self) -> int:
+        return len(self._live)
+
+    def submit(self, q: Query) -> None:
+        if not (0 <= q.graph < len(self.sizes)):
+            raise AdmissionError(f"query {q.qid}: graph {q.graph} not in the pool")
+        if not (0 <= q.source < self.sizes[q.graph]):
+            raise AdmissionError(f"query {q.qid}: source {q.source} out of range")
+        if self.cost(q) > self.budget:
+            raise AdmissionError(f"query {q.qid}: needs {self.cost(q)} bytes, budget {self.budget}")
+        self._order.append(q.qid)
+        self._by_graph[q.graph].append(q)
+        self._live[q.qid] = q
+
+    def take_batch(self) -> List[Query]:
+        while self._order and self._order[0] not in self._live:
+            self._order.popleft()
+        if not self._order:
+            return []
+        head = self._live[self._order[0]]
+        dq = self._by_graph[head.graph]
+        batch: List[Query] = []
+        while dq and len(batch) < self.max_lanes:
+            q = dq[0]
+            c = self.cost(q)
+            if self.used + c > self.budget:
+                break
+            dq.popleft()
+            self.used += c
+            del self._live[q.qid]
+            batch.append(q)
+        self.peak_used = max(self.peak_used, self.used)
+        return batch
+
+    def release(self, batch: Sequence[Query]) -> None:
+        for q in batch:
+            self.used -= self.cost(q)
+        if self.used < 0:
+            raise RuntimeError("scheduler released more memory than it admitted")
+
+
+# ---------------------------------------------------------------------------
+# serving loop
+
+def serve(ex, sched: Scheduler, queries: Sequence[Query],
+          on_done: Optional[Callable] = None) -> List[Query]:
+    """Run every query to completion.  ``queries`` are sorted by arrival on
+    the executor's clock (seconds from the start of the call)."""
+    queries = sorted(queries, key=lambda q: (q.arrival, q.qid))
+    nq = len(queries)
+    i = 0
+    inflight: Dict[int, List[Query]] = {}
+    free = list(range(ex.slots))[::-1]
+    finished: List[Query] = []
+    ex.start()
+    while i < nq or sched.pending or inflight:
+        progressed = False
+        now = ex.now()
+        while i < nq and queries[i].arrival <= now:
+            sched.submit(queries[i])
+            i += 1
+            progressed = True
+        for slot in list(inflight):
+            if ex.poll(slot):
+                t = ex.now()
+                batch = inflight.pop(slot)
+                for q in batch:
+                    q.done = t
+                if on_done is not None:
+                    on_done(batch, ex.outputs(slot))
+                ex.retire(slot)
+                sched.release(batch)
+                free.append(slot)
+                finished.extend(batch)
+                progressed = True
+        while free:
+            batch = sched.take_batch()
+            if not batch:
+                break
+            slot = free.pop()
+            t = ex.now()
+            for q in batch:
+                q.start = t
+                q.batch_size = len(batch)
+            ex.launch(slot, batch)
+            inflight[slot] = batch
+            progressed = True
+        if not progressed:
+            ex.idle(queries[i].arrival if i < nq else None)
+    return finished
+
+
+def latency_summary(done: Sequence[Query], skip: int = 0) -> dict:
+    """p50/p99/mean latency (ms) and throughput over queries after ``skip``
+    warm-up queries (in arrival order)."""
+    qs = sorted(done, key=lambda q: (q.arrival, q.qid))[skip:]
+    if not qs:
+        return {"queries": 0}
+    lat = np.array([q.latency for q in qs]) * 1e3
+    span = max(q.done for q in qs) - min(q.arrival for q in qs)
+    return {"queries": len(qs),
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()),
+            "max_ms": float(lat.max()),
+            "throughput_qps": len(qs) / span if span > 0 else float("inf"),
+            "mean_batch": float(np.mean([q.batch_size for q in qs]))}
+
+
+# ---------------------------------------------------------------------------
+# workload: arrivals
+
+def poisson_queries(rate: float, count: int, graph_sources: Sequence[np.ndarray], seed: int,
+                    first_id: int = 0) -> List[Query]:
+    """``count`` queries with exponential inter-arrival times of mean 1/rate
+    (rate <= 0 or inf: every query arrives at time 0, the closed backlog used
+    to measure saturation throughput).  Graph uniform over the pool, source
+    uniform over that graph's candidate vertices (``graph_sources[g]``)."""
+    rng = np.random.default_rng(seed)
+    if rate > 0 and math.isfinite(rate):
+        t = np.cumsum(rng.exponential(1.0 / rate, count))
+    else:
+        t = np.zeros(count)
+    gs = rng.integers(0, len(graph_sources), count)
+    out = []
+    for k in range(count):
+        cand = graph_sources[int(gs[k])]
+        s = int(cand[int(rng.integers(0, len(cand)))])
+        out.append(Query(first_id + k, int(gs[k]), s, float(t[k])))
+    return out
+
+
+def nonzero_degree_vertices(n: int, src: np.ndarray, dst: np.ndarray) -> np.ndarray:
+    """Vertices with at least one edge to another vertex (query sources)."""
+    keep = src != dst
+    deg = np.bincount(src[keep], minlength=n) + np.bincount(dst[keep], minlength=n)
+    return np.nonzero(deg)[0].astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# executors
+
+class SimExecutor:
+    """Simulated device for host-only tests: a launch of L lanes on a graph
+    of n vertices takes ``service(n, L)`` seconds of simulated time, and
+    ``slots`` launches may run at once."""
+
+    def __init__(self, slots: int, service: Callable[[int, int], float], sizes: Sequence[int]):
+        self.slots = slots
+        self.service = service
+        self.sizes = list(sizes)
+        self.t = 0.0
+        self.finish: Dict[int, float] = {}
+        self.batches: Dict[int, List[Query]] = {}
+        self.max_inflight = 0
+        self.launches: List[tuple] = []
+
+    def start(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def launch(self, slot: int, batch: List[Query]):
+        assert slot not in self.finish, "launch on a busy slot"
+        n = self.sizes[batch[0].graph]
+        self.finish[slot] = self.t + self.service(n, len(batch))
+        self.batches[slot] = batch
+        self.max_inflight = max(self.max_inflight, len(self.finish))
+        self.launches.append((self.t, slot, [q.qid for q in batch]))
+
+    def poll(self, slot: int) -> bool:
+        return self.finish[slot] <= self.t
+
+    def outputs(self, slot: int):
+        return None
+
+    def retire(self, slot: int):
+        del self.finish[slot]
+        del self.batches[slot]
+
+    def idle(self, next_arrival: Optional[float]):
+        cands = list(self.finish.values())
+        if next_arrival is not None:
+            cands.append(next_arrival)
+        if not cands:
+            raise RuntimeError("serving loop idle with nothing pending")
+        self.t = max(self.t, min(cands))
+
+
+class GpuExecutor:
+    """Runs batches through the library on ``slots`` HIP streams.
+
+    A batch of at least ``min_batch_lanes`` queries is one multi-source
+    launch; a smaller one is that many single-source searches queued on the
+    slot's stream.  Outputs are allocated on the slot's stream when the
+    batch is launched and released when the host retires it.
+    """
+
+    def __init__(self, graphs: Sequence, slots: int = 4, min_batch_lanes: int = 8):
+        import torch
+        from . import gapbfs as gb
+        self.torch = torch
+        self.gb = gb
+        self.graphs = list(graphs)
+        self.slots = int(slots)
+        self.min_batch_lanes = int(min_batch_lanes)
+        self._saved_params = gb.get_params()
+        gb.set_params(grid_split=self.slots)
+        self.streams = [torch.cuda.Stream() for _ in range(self.slots)]
+        self.events = [torch.cuda.Event() for _ in range(self.slots)]
+        self.out: Dict[int, tuple] = {}
+        self.t0 = 0.0
+
+    def start(self):
+        self.torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def launch(self, slot: int, batch: List[Query]):
+        torch, gb = self.torch, self.gb
+        st = self.streams[slot]
+        g = self.graphs[batch[0].graph]
+        with torch.cuda.stream(st):
+            ps = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in batch]
+            ds = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in batch]
+            if len(batch) >= self.min_batch_lanes:
+                gb.bfs_batch([g], [0] * len(batch), [q.source for q in batch], ps, ds, stream=st)
+            else:
+                for q, p, d in zip(batch, ps, ds):
+                    gb.bfs(g, q.source, p, d, stream=st)
+            self.events[slot].record(st)
+        self.out[slot] = (ps, ds)
+
+    def poll(self, slot: int) -> bool:
+        return self.events[slot].query()
+
+    def outputs(self, slot: int):
+        return self.out[slot]
+
+    def retire(self, slot: int):
+        del self.out[slot]
+
+    def close(self):
+        """Wait for the streams and restore the process-wide parameters."""
+        self.torch.cuda.synchronize()
+        self.out.clear()
+        self.gb.set_params(**self._saved_params)
+
+    def idle(self, next_arrival: Optional[float]):
+        # spin briefly: launches complete within tens of microseconds to
+        # milliseconds, and the host clock decides the latency measured
+        if next_arrival is not None:
+            wait = next_arrival - self.now()
+            if wait > 2e-4:
+                time.sleep(min(wait, 1e-3) * 0.5)
+
+
+# ---------------------------------------------------------------------------
+# resident pool
+
+def pool_spec(small: bool = False) -> List[tuple]:
+    """The serving pool: R-MAT scales 14..20 with 3 seeds each and scales 21
+    and 22 with 2 seeds each (25 graphs), and road-like grids of side 512,
+    768, ..., 2048 (7 graphs).  ``small`` gives a 6-graph pool for tests."""
+    if small:
+        return [("rmat", 10, 50000), ("rmat", 11, 50001), ("rmat", 12, 50002),
+                ("grid", 48, 50003), ("grid", 80, 50004), ("rmat", 9, 50005)]
+    spec, j = [], 0
+    for scale in range(14, 21):
+        for _ in range(3):
+            spec.append(("rmat", scale, 50000 + j))
+            j += 1
+    for scale in (21, 22):
+        for _ in range(2):
+            spec.append(("rmat", scale, 50000 + j))
+            j += 1
+    for side in (512, 768, 1024, 1280, 1536, 1792, 2048):
+        spec.append(("grid", side, 50000 + j))
+        j += 1
+    return spec
+
+
+def pool_edges(kind: str, size: int, seed: int):
+    from . import inputs
+    if kind == "rmat":
+        return inputs.rmat(size, 16, seed=seed)
+    if kind == "grid":
+        return inputs.grid(size, size, seed=seed)
+    raise KeyError(kind)
+
+
+class Pool:
+    """Graphs of ``spec`` built into device memory, with the candidate
+    sources of each (vertices of non-zero degree)."""
+
+    def __init__(self, spec: Sequence[tuple], keep_edges: bool = False):
+        from . import gapbfs as gb
+        self.spec = list(spec)
+        self.graphs, self.sources, self.edges = [], [], []
+        for kind, size, seed in self.spec:
+            el = pool_edges(kind, size, seed)
+            self.graphs.append(gb.build_csr(el.n, el.src, el.dst))
+            self.sources.append(nonzero_degree_vertices(el.n, el.src, el.dst))
+            self.edges.append(el if keep_edges else None)
+
+    @property
+    def sizes(self) -> List[int]:
+        return [g.n for g in self.graphs]
+
+    def workspace_bytes(self, slots: int, max_lanes: int) -> int:
+        """Upper bound of the library workspaces the serving streams hold."""
+        return slots * batch_workspace_bytes(max(self.sizes), max_lanes)
+
+    def free(self):
+        for g in self.graphs:
+            g.free()
+        self.graphs = []

@@ -179,6 +179,42 @@ def test_two_streams_concurrently(gpu):
         assert_valid(A, src, p.cpu().numpy(), d.cpu().numpy())
 
 
+@pytest.mark.parametrize("split", [2, 3, 4])
+def test_grid_split_streams_overlap(gpu, split):
+    """With grid_split = k, k persistent launches (single and batched) run at
+    once on k streams; every result stays exact."""
+    import torch
+    from paper_1508_03619_amd import inputs
+    el = inputs.rmat(14, 16, seed=43)
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    srcs = [int(x) for x in inputs.pick_sources(el, 24, seed=44)]
+    saved = gpu.get_params()
+    gpu.set_params(grid_split=split)
+    streams = [torch.cuda.Stream() for _ in range(split + 1)]
+    outs = []
+    say(f"grid_split={split}")
+    try:
+        for i, src in enumerate(srcs):
+            st = streams[i % len(streams)]
+            with torch.cuda.stream(st):
+                if i % 4 == 3:
+                    lanes = srcs[i - 3:i + 1]
+                    ps = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in lanes]
+                    ds = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in lanes]
+                    gpu.bfs_batch([g], [0] * len(lanes), lanes, ps, ds, stream=st)
+                    outs += list(zip(lanes, ps, ds))
+                else:
+                    p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+                    d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+                    gpu.bfs(g, src, p, d, stream=st)
+                    outs.append((src, p, d))
+        torch.cuda.synchronize()
+    finally:
+        gpu.set_params(**saved)
+    for src, p, d in outs:
+        assert_valid(A, src, p.cpu().numpy(), d.cpu().numpy(), what=f"split={split}")
+
+
 def test_grid_road_like(gpu):
     from paper_1508_03619_amd import inputs
     el = inputs.grid(300, 200, seed=7)

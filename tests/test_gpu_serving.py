@@ -1,0 +1,60 @@
+"""Serving parity: every query served in the mix (batched with others of its
+graph, several launches in flight) has the depth array it has alone, and
+both parent arrays are valid (Section 2.1); depths also equal the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpuutil import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_serving_mix_equals_alone(gpu):
+    import torch
+    from paper_1508_03619_amd import serving as sv
+    pool = sv.Pool(sv.pool_spec(small=True), keep_edges=True)
+    adjs = [oracle.Adjacency(el.n, el.src, el.dst) for el in pool.edges]
+    # a backlog (large batches) followed by Poisson arrivals (small batches
+    # and single-source launches while earlier launches run)
+    qs = sv.poisson_queries(0.0, 150, pool.sources, seed=777)
+    tail = sv.poisson_queries(4000.0, 150, pool.sources, seed=778, first_id=150)
+    qs += tail
+    results = {}
+
+    def on_done(batch, outs):
+        for q, p, d in zip(batch, *outs):
+            results[q.qid] = (p.cpu().numpy(), d.cpu().numpy())
+
+    say(f"serving {len(qs)} queries over {len(pool.graphs)} graphs, 4 slots")
+    sched = sv.Scheduler(pool.sizes, budget_bytes=1 << 28, max_lanes=64)
+    ex = sv.GpuExecutor(pool.graphs, slots=4, min_batch_lanes=4)
+    try:
+        done = sv.serve(ex, sched, qs, on_done)
+    finally:
+        ex.close()
+    assert sorted(q.qid for q in done) == list(range(300))
+    sizes = [q.batch_size for q in done]
+    assert max(sizes) >= 4 and min(sizes) < 4, "both launch kinds must be exercised"
+    say("serving: checking each query alone")
+    refs = {}
+    p1 = {}
+    for q in done:
+        A = adjs[q.graph]
+        key = (q.graph, q.source)
+        if key not in refs:
+            refs[key] = A.bfs(q.source)[0]
+        pm, dm = results[q.qid]
+        assert A.check(q.source, refs[key], pm, dm)[0] == 0, f"query {q.qid} in the mix"
+        g = pool.graphs[q.graph]
+        if g.n not in p1:
+            p1[g.n] = (torch.empty(g.n, dtype=torch.int32, device="cuda"),
+                       torch.empty(g.n, dtype=torch.int32, device="cuda"))
+        pa, da = p1[g.n]
+        from paper_1508_03619_amd import gapbfs as gb
+        gb.bfs(g, q.source, pa, da)
+        torch.cuda.synchronize()
+        pa_h, da_h = pa.cpu().numpy(), da.cpu().numpy()
+        assert np.array_equal(da_h, dm), f"query {q.qid}: depth alone != depth in the mix"
+        assert A.check(q.source, refs[key], pa_h, da_h)[0] == 0, f"query {q.qid} alone"
+    pool.free()

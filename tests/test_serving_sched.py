@@ -1,0 +1,134 @@
+"""Serving loop host logic on a simulated clock: admission against the
+memory budget, FIFO order, same-graph batching, slot limits, latency
+accounting.  No device is used."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1508_03619_amd import serving as sv
+
+
+def linear_service(n, lanes):
+    return 1e-4 + 1e-9 * n * (1 + 0.05 * lanes)
+
+
+SIZES = [1 << 10, 1 << 12, 1 << 14, 5000]
+
+
+def make_queries(rate, count, seed=777):
+    cands = [np.arange(n, dtype=np.int32) for n in SIZES]
+    return sv.poisson_queries(rate, count, cands, seed)
+
+
+class Recorder(sv.SimExecutor):
+    """SimExecutor that checks the budget at every launch."""
+
+    def __init__(self, sched, *a, **k):
+        super().__init__(*a, **k)
+        self.sched = sched
+        self.max_used = 0
+
+    def launch(self, slot, batch):
+        assert self.sched.used <= self.sched.budget
+        self.max_used = max(self.max_used, self.sched.used)
+        super().launch(slot, batch)
+
+
+@pytest.mark.parametrize("rate", [50.0, 2000.0, 0.0])
+def test_every_query_completes_once(rate):
+    qs = make_queries(rate, 500)
+    sched = sv.Scheduler(SIZES, budget_bytes=64 * 8 * max(SIZES), max_lanes=16)
+    ex = Recorder(sched, 3, linear_service, SIZES)
+    done = sv.serve(ex, sched, qs)
+    assert sorted(q.qid for q in done) == list(range(500))
+    assert sched.used == 0 and sched.pending == 0
+    for q in done:
+        assert q.arrival <= q.start <= q.done
+        assert 1 <= q.batch_size <= 16
+    assert ex.max_inflight <= 3
+
+
+def test_batches_hold_one_graph_in_arrival_order():
+    qs = make_queries(0.0, 300, seed=5)
+    sched = sv.Scheduler(SIZES, budget_bytes=1 << 30, max_lanes=8)
+    ex = sv.SimExecutor(2, linear_service, SIZES)
+    sv.serve(ex, sched, qs)
+    byid = {q.qid: q for q in qs}
+    seen = set()
+    for _, _, ids in ex.launches:
+        assert len({byid[i].graph for i in ids}) == 1
+        assert ids == sorted(ids)        # arrival order inside a batch
+        assert len(ids) <= 8
+        seen.update(ids)
+    assert seen == set(range(300))
+    # the head of line is always in the next batch: launches start with the
+    # oldest query not yet launched
+    launched = set()
+    for _, _, ids in ex.launches:
+        oldest = min(set(range(300)) - launched)
+        assert oldest in ids
+        launched.update(ids)
+
+
+def test_budget_is_never_exceeded_and_blocks_admission():
+    # budget for only 3 outputs of the largest graph
+    budget = 3 * sv.query_output_bytes(max(SIZES))
+    qs = make_queries(0.0, 200, seed=9)
+    sched = sv.Scheduler(SIZES, budget_bytes=budget, max_lanes=64)
+    ex = Recorder(sched, 4, linear_service, SIZES)
+    done = sv.serve(ex, sched, qs)
+    assert len(done) == 200
+    assert sched.peak_used <= budget
+    assert ex.max_used <= budget
+    # a budget that admits 3 large outputs cannot put 4 of them in flight
+    big = [q for q in done if SIZES[q.graph] == max(SIZES)]
+    assert big
+    for q in big:
+        overlapping = [r for r in big if r.start < q.done and q.start < r.done]
+        assert len(overlapping) <= 3
+
+
+def test_query_larger_than_budget_is_rejected():
+    sched = sv.Scheduler(SIZES, budget_bytes=sv.query_output_bytes(SIZES[0]))
+    with pytest.raises(sv.AdmissionError):
+        sched.submit(sv.Query(0, 2, 0, 0.0))
+    with pytest.raises(sv.AdmissionError):
+        sched.submit(sv.Query(1, 7, 0, 0.0))
+    with pytest.raises(sv.AdmissionError):
+        sched.submit(sv.Query(2, 0, SIZES[0], 0.0))
+
+
+def test_new_arrivals_do_not_wait_for_running_batches():
+    # one long launch in flight; a query arriving later starts on a free slot
+    sizes = [1000, 1000]
+    service = lambda n, lanes: 1.0 if lanes > 1 else 0.01
+    qs = [sv.Query(i, 0, i, 0.0) for i in range(4)] + [sv.Query(4, 1, 0, 0.5)]
+    sched = sv.Scheduler(sizes, budget_bytes=1 << 30, max_lanes=64)
+    ex = sv.SimExecutor(2, service, sizes)
+    done = {q.qid: q for q in sv.serve(ex, sched, qs)}
+    assert done[4].start == pytest.approx(0.5)
+    assert done[4].done == pytest.approx(0.51)
+    assert done[0].done == pytest.approx(1.0)
+
+
+def test_latency_summary_and_poisson_rate():
+    qs = make_queries(1000.0, 4000, seed=11)
+    gaps = np.diff([q.arrival for q in qs])
+    assert abs(gaps.mean() - 1e-3) < 1e-4            # mean inter-arrival 1/rate
+    assert abs(np.std(gaps) / gaps.mean() - 1) < 0.1  # exponential: cv = 1
+    counts = np.bincount([q.graph for q in qs], minlength=len(SIZES))
+    assert counts.min() > 0.2 * len(qs) / len(SIZES) * 3.5
+    for q in qs:
+        q.start, q.done, q.batch_size = q.arrival, q.arrival + 0.002, 1
+    s = sv.latency_summary(qs, skip=100)
+    assert s["queries"] == 3900
+    assert s["p50_ms"] == pytest.approx(2.0) and s["p99_ms"] == pytest.approx(2.0)
+
+
+def test_workspace_bound_matches_layout():
+    # one 64-lane segment of n vertices: 24n (bitsets) + 512n (lane staging) + 128n (queues)
+    n = 1 << 16
+    assert sv.batch_workspace_bytes(n, 64) == 664 * n
+    assert sv.batch_workspace_bytes(n, 65) == (48 + 1024 + 128) * n
+    assert sv.batch_workspace_bytes(n, 300) == 2 * (96 + 2048 + 128) * n
