@@ -79,6 +79,181 @@ class GraphCase:
             f"built in {time.time() - t0:.1f}s")
 
 
+def component_edges(g, el):
+    """Per-vertex count of undirected edges in its connected component
+    (m_s of a search from that vertex), from the device CSR's degrees and
+    scipy's connected components of the raw edge list."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    rp, _ = g.export_row_ptr()
+    deg = np.diff(rp)
+    keep = el.src != el.dst
+    A = sp.coo_matrix((np.ones(int(keep.sum()), np.int8), (el.src[keep], el.dst[keep])),
+                      shape=(el.n, el.n)).tocsr()
+    _, lab = connected_components(A, directed=False)
+    per_comp = np.bincount(lab, weights=deg, minlength=lab.max() + 1) // 2
+    return per_comp[lab].astype(np.int64)
+
+
+def time_launches(torch, stream, fn, reps=3):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def leg_grid(gb, torch, inputs, stream):
+    """4096^2 road-like grid: 64 single-source searches, persistent kernel vs
+    captured level graphs (level count and time per level)."""
+    t0 = time.time()
+    el = inputs.workload("grid4096")
+    g = gb.build_csr(el.n, el.src, el.dst)
+    srcs = [int(x) for x in inputs.pick_sources(el, 64, seed=inputs.SOURCE_SEEDS["grid4096"])]
+    ce = component_edges(g, el)
+    p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    levels = []
+    for s in srcs[:8]:
+        levels.append(len(gb.bfs(g, s, p, d, stats=True, max_levels=1 << 16)))
+    out = {"n": g.n, "nnz": g.nnz, "levels_mean_first8": float(np.mean(levels)),
+           "build_s": round(time.time() - t0, 1)}
+    ms = sum(int(ce[s]) for s in srcs)
+    for mode, label in ((0, "persistent"), (2, "graph")):
+        prm = {"mode": mode}
+        gb.bfs(g, srcs[0], p, d, params=prm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for s in srcs:
+            gb.bfs(g, s, p, d, params=prm)
+        e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1)
+        out[label] = {"ms_per_search": round(t / len(srcs), 3), "gteps": round(ms / (t * 1e-3) / 1e9, 3),
+                      "us_per_level": round(t / len(srcs) / np.mean(levels) * 1e3, 2)}
+        log(f"grid4096 {label}: {out[label]}")
+    g.free()
+    return out
+
+
+def leg_rmat24(gb, torch, inputs, stream):
+    """R-MAT scale 24: batches of 64 and 256 sources vs the same sources one
+    by one (per-source throughput)."""
+    el = inputs.workload("rmat24")
+    g = gb.build_csr(el.n, el.src, el.dst)
+    srcs = [int(x) for x in inputs.pick_sources(el, 256, seed=inputs.SOURCE_SEEDS["rmat24"])]
+    ce = component_edges(g, el)
+    del el
+    out = {"n": g.n, "nnz": g.nnz}
+    p1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    d1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    single = time_launches(torch, stream, lambda: [gb.bfs(g, s, p1, d1) for s in srcs[:64]], reps=2)
+    for L in (64, 256):
+        P = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(L)]
+        D = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(L)]
+        t = time_launches(torch, stream, lambda: gb.bfs_batch([g], [0] * L, srcs[:L], P, D), reps=2)
+        ms = sum(int(ce[s]) for s in srcs[:L])
+        out[f"batch{L}"] = {"ms": round(t, 3), "gteps": round(ms / (t * 1e-3) / 1e9, 2),
+                            "output_floor_ms": round(8 * L * g.n / HBM_PEAK_GBS / 1e6, 3)}
+        del P, D
+        torch.cuda.empty_cache()
+    ms64 = sum(int(ce[s]) for s in srcs[:64])
+    out["single64"] = {"ms_sum": round(single, 3), "gteps": round(ms64 / (single * 1e-3) / 1e9, 2)}
+    out["batch64_speedup_vs_single"] = round(single / out["batch64"]["ms"], 2)
+    log(f"rmat24: {out}")
+    g.free()
+    return out
+
+
+MIXED_SCALES = [14, 14, 15, 15, 16, 16, 17, 17, 18, 18, 19, 19, 20, 20, 20, 20]
+
+
+def leg_mixed(gb, torch, inputs, stream):
+    """16 R-MAT graphs of scales 14-20 in one launch: 4 and 16 sources per
+    graph (64 and 256 lanes)."""
+    els = [inputs.rmat(s, 16, seed=30000 + i) for i, s in enumerate(MIXED_SCALES)]
+    graphs = [gb.build_csr(e.n, e.src, e.dst) for e in els]
+    ces = [component_edges(g, e) for g, e in zip(graphs, els)]
+    out = {"sum_n": int(sum(g.n for g in graphs)), "sum_nnz": int(sum(g.nnz for g in graphs))}
+    for per in (4, 16):
+        gos, srcs = [], []
+        for gi, e in enumerate(els):
+            for s in inputs.pick_sources(e, per, seed=1030000 + gi):
+                gos.append(gi)
+                srcs.append(int(s))
+        P = [torch.empty(graphs[gi].n, dtype=torch.int32, device="cuda") for gi in gos]
+        D = [torch.empty(graphs[gi].n, dtype=torch.int32, device="cuda") for gi in gos]
+        t = time_launches(torch, stream, lambda: gb.bfs_batch(graphs, gos, srcs, P, D))
+        pa, da = P[0], D[0]
+        single = time_launches(torch, stream, lambda: [gb.bfs(graphs[gi], s, P[i], D[i])
+                                                       for i, (gi, s) in enumerate(zip(gos, srcs))],
+                               reps=2)
+        ms = sum(int(ces[gi][s]) for gi, s in zip(gos, srcs))
+        out[f"lanes{len(srcs)}"] = {"batch_ms": round(t, 3), "batch_gteps": round(ms / (t * 1e-3) / 1e9, 2),
+                                    "single_ms_sum": round(single, 3),
+                                    "batch_speedup_vs_single": round(single / t, 2)}
+        del P, D, pa, da
+    log(f"mixed16: {out}")
+    for g in graphs:
+        g.free()
+    return out
+
+
+def leg_serving(gb, torch, nq):
+    """Serving pool of 32 resident graphs: saturation throughput from a closed
+    backlog, then Poisson arrivals at 0.25, 0.6 and 0.9 of it."""
+    from paper_1508_03619_amd import serving as sv
+    t0 = time.time()
+    spec = sv.pool_spec()
+    pool = sv.Pool(spec, keep_edges=True)
+    ces = [component_edges(g, el) for g, el in zip(pool.graphs, pool.edges)]
+    pool.edges = [None] * len(pool.edges)
+    slots, lanes, min_lanes = 4, 64, 8
+    budget = 8 << 30
+    ex = sv.GpuExecutor(pool.graphs, slots=slots, min_batch_lanes=min_lanes)
+    out = {"graphs": len(pool.graphs), "sum_n": int(sum(pool.sizes)), "slots": slots,
+           "max_lanes": lanes, "min_batch_lanes": min_lanes, "budget_bytes": budget,
+           "workspace_bound_bytes": pool.workspace_bytes(slots, lanes),
+           "build_s": round(time.time() - t0, 1)}
+
+    def run(rate, n, seed):
+        qs = sv.poisson_queries(rate, n, pool.sources, seed)
+        sched = sv.Scheduler(pool.sizes, budget_bytes=budget, max_lanes=lanes)
+        t = time.perf_counter()
+        done = sv.serve(ex, sched, qs)
+        wall = time.perf_counter() - t
+        summ = sv.latency_summary(done, skip=n // 10)
+        kept = sorted(done, key=lambda q: (q.arrival, q.qid))[n // 10:]
+        span = max(q.done for q in kept) - min(q.arrival for q in kept)
+        summ["gteps"] = sum(int(ces[q.graph][q.source]) for q in kept) / span / 1e9
+        summ["peak_admitted_bytes"] = sched.peak_used
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}, wall
+
+    try:
+        run(0.0, 300, 1)  # warm-up: workspaces, code objects
+        s, wall = run(0.0, nq, 776)
+        rsat = nq / wall
+        out["r_sat_qps"] = round(rsat, 1)
+        out["closed"] = s
+        log(f"serving closed backlog: R_sat={rsat:.1f} q/s {s}")
+        for k, f in enumerate((0.25, 0.6, 0.9)):
+            s, wall = run(f * rsat, nq, 777 + k)
+            s["offered_qps"] = round(f * rsat, 1)
+            out[f"rate_{f}"] = s
+            log(f"serving at {f} R_sat: {s}")
+    finally:
+        ex.close()
+        pool.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +264,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", default="rmat22,urand22")
+    ap.add_argument("--legs", default="serving",
+                    help="comma list of extra legs reported in detail: serving, grid4096, rmat24, "
+                         "mixed, or all")
+    ap.add_argument("--serve-queries", type=int, default=1500)
     ap.add_argument("--profile-leg", action="store_true",
                     help="for rocprofv3 counter runs: a copy of known size, then one search per "
                          "source, no timing and no JSON")
@@ -251,6 +430,21 @@ def main():
             detail[c.name]["single64_ms_sum"] = round(single_ms, 3)
             detail[c.name]["batch_speedup_vs_single"] = round(single_ms / bt, 2)
             del parents, depths
+
+    legs = set(args.legs.split(",")) if args.legs else set()
+    if "all" in legs:
+        legs = {"serving", "grid4096", "rmat24", "mixed"}
+    for c in cases:
+        c.parent = c.depth = None
+    torch.cuda.empty_cache()
+    if "grid4096" in legs:
+        detail["grid4096"] = leg_grid(gb, torch, inputs, stream)
+    if "rmat24" in legs:
+        detail["rmat24"] = leg_rmat24(gb, torch, inputs, stream)
+    if "mixed" in legs:
+        detail["mixed16"] = leg_mixed(gb, torch, inputs, stream)
+    if "serving" in legs:
+        detail["serving"] = leg_serving(gb, torch, args.serve_queries)
 
     cpu = None
     if not args.no_cpu_baseline:

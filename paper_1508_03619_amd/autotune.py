@@ -1,0 +1,230 @@
+"""Offline tuner: one parameter set per GPU model, used for every graph.
+
+Section 2.3 allows one implementation and one set of tuning parameters for
+all input graphs.  This tuner therefore searches only hardware-facing
+parameters (direction-switch thresholds, workgroup size, hub splitting, the
+level schedule, the batched thresholds) on a fixed tuning set of graphs of
+the benchmark's three shapes at reduced size (R-MAT, uniform random,
+road-like grid, and a mixed multi-source batch), and writes the winner to
+``tuned/<arch>_<CUs>cu.json``.  The binding applies that file when it loads
+the library on a device of that model.  Parameters never change results:
+depths are unique and every schedule returns valid parents.
+
+Search: coordinate descent from the library defaults; each coordinate takes
+the value of least score, where the score is the geometric mean over the
+tuning items of (time with the candidate set) / (time with the defaults).
+
+    python -m paper_1508_03619_amd.autotune [--passes 2] [--dry-run]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from typing import Callable, Dict, List, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+TUNED_DIR = os.path.join(_HERE, "tuned")
+
+# Candidate values per parameter (all legal for gap_set_params).
+SPACE: Dict[str, List[int]] = {
+    "alpha": [4, 8, 12, 15, 20, 30, 50],
+    "beta": [6, 12, 18, 24, 48, 96],
+    "block": [256, 512, 1024],
+    "hub_degree": [64, 128, 256, 512, 1024],
+    "chunk_edges": [128, 256, 512, 1024],
+    "mode": [0, 2],
+    "graph_chunk": [8, 16, 32, 64],
+    "batch_alpha": [2, 4, 8, 15, 30],
+    "batch_beta": [6, 12, 18, 36, 72],
+}
+ORDER = ["block", "alpha", "beta", "hub_degree", "chunk_edges", "batch_alpha", "batch_beta",
+         "mode", "graph_chunk"]
+
+# Tuning set: the benchmark's graph shapes at reduced size, other seeds.
+TUNING_SET = [
+    {"kind": "single", "graph": ("rmat", 20, 7001), "sources": 8},
+    {"kind": "single", "graph": ("urand", 20, 7002), "sources": 8},
+    {"kind": "single", "graph": ("grid", 1024, 7003), "sources": 4},
+    {"kind": "batch", "graphs": [("rmat", 20, 7001)], "lanes": 64},
+    {"kind": "batch", "graphs": [("rmat", s, 7100 + s) for s in (14, 15, 16, 17, 18)], "lanes": 16},
+]
+
+
+def arch_key(arch: str, cus: int) -> str:
+    return f"{arch.split(':')[0]}_{int(cus)}cu"
+
+
+def tuned_path(arch: str, cus: int) -> str:
+    return os.path.join(TUNED_DIR, arch_key(arch, cus) + ".json")
+
+
+def read_tuned(path: str) -> dict:
+    with open(path) as f:
+        d = json.load(f)
+    params = d.get("params", {})
+    for k, v in params.items():
+        if not isinstance(v, int):
+            raise ValueError(f"{path}: parameter {k} is not an integer")
+    return params
+
+
+def coordinate_descent(space: Dict[str, Sequence[int]], order: Sequence[str], start: Dict[str, int],
+                       score: Callable[[Dict[str, int]], float], passes: int = 2,
+                       min_gain: float = 0.01, log=print) -> tuple:
+    """Minimise ``score`` one coordinate at a time.  A new value must beat the
+    incumbent by ``min_gain`` (relative) to be taken.  Returns (best params,
+    best score, number of evaluations)."""
+    cache: Dict[tuple, float] = {}
+
+    def ev(p):
+        key = tuple(sorted(p.items()))
+        if key not in cache:
+            cache[key] = score(p)
+        return cache[key]
+
+    best = dict(start)
+    best_s = ev(best)
+    for ps in range(passes):
+        changed = False
+        for name in order:
+            for v in space[name]:
+                if v == best[name]:
+                    continue
+                cand = dict(best)
+                cand[name] = v
+                s = ev(cand)
+                if s < best_s * (1.0 - min_gain):
+                    log(f"  pass {ps}: {name}={v} score {s:.4f} (was {best_s:.4f})")
+                    best, best_s, changed = cand, s, True
+        if not changed:
+            break
+    return best, best_s, len(cache)
+
+
+# ---------------------------------------------------------------------------
+# measurement on the device
+
+class _Bench:
+    def __init__(self):
+        import torch
+        from . import gapbfs as gb, inputs
+        from .serving import pool_edges
+        self.torch, self.gb = torch, gb
+        self.graphs = {}
+        self.sources = {}
+        self.items = []
+        for it in TUNING_SET:
+            keys = [it["graph"]] if it["kind"] == "single" else it["graphs"]
+            for key in keys:
+                if key not in self.graphs:
+                    el = pool_edges(*key)
+                    self.graphs[key] = gb.build_csr(el.n, el.src, el.dst)
+                    self.sources[key] = [int(x) for x in inputs.pick_sources(el, 64, seed=key[2] + 1)]
+            self.items.append(it)
+        nmax = max(g.n for g in self.graphs.values())
+        self.buf = [(torch.empty(nmax, dtype=torch.int32, device="cuda"),
+                     torch.empty(nmax, dtype=torch.int32, device="cuda")) for _ in range(80)]
+        self.stream = torch.cuda.current_stream()
+
+    def _time(self, fn) -> float:
+        torch = self.torch
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        fn()  # warm-up (also sizes the workspace)
+        best = math.inf
+        for _ in range(2):
+            a.record(self.stream)
+            fn()
+            b.record(self.stream)
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+        return best
+
+    def measure(self, params: Dict[str, int]) -> List[float]:
+        gb = self.gb
+        gb.set_params(**params)
+        out = []
+        for it in self.items:
+            if it["kind"] == "single":
+                g = self.graphs[it["graph"]]
+                srcs = self.sources[it["graph"]][:it["sources"]]
+
+                def fn(g=g, srcs=srcs):
+                    p, d = self.buf[0]
+                    for s in srcs:
+                        gb.bfs(g, s, p, d)
+            else:
+                keys = it["graphs"]
+                gl = [self.graphs[k] for k in keys]
+                gos, srcs = [], []
+                for gi, k in enumerate(keys):
+                    for s in self.sources[k][:it["lanes"]]:
+                        gos.append(gi)
+                        srcs.append(s)
+
+                def fn(gl=gl, gos=gos, srcs=srcs):
+                    ps = [self.buf[i][0] for i in range(len(srcs))]
+                    ds = [self.buf[i][1] for i in range(len(srcs))]
+                    gb.bfs_batch(gl, gos, srcs, ps, ds)
+            out.append(self._time(fn))
+        return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--dry-run", action="store_true", help="print the result, write nothing")
+    ap.add_argument("--out", default=None, help="write here instead of tuned/<model>.json")
+    args = ap.parse_args(argv)
+    from . import gapbfs as gb
+    gb.load()
+    dev = gb.device_query()
+    defaults = gb.library_defaults()
+    log = lambda m: print(f"[autotune] {m}", flush=True)
+    log(f"device {dev['arch']} with {dev['compute_units']} CUs")
+    t0 = time.time()
+    bench = _Bench()
+    base_params = {k: defaults[k] for k in ORDER}
+    base = bench.measure(defaults)
+    log("defaults: " + ", ".join(f"{b:.3f}" for b in base) + " ms")
+
+    def score(p):
+        full = dict(defaults)
+        full.update(p)
+        t = bench.measure(full)
+        return math.exp(sum(math.log(x / y) for x, y in zip(t, base)) / len(t))
+
+    best, best_s, nev = coordinate_descent(SPACE, ORDER, base_params, score, passes=args.passes,
+                                           log=log)
+    full = dict(defaults)
+    full.update(best)
+    tuned_ms = bench.measure(full)
+    gb.set_params(**defaults)
+    result = {
+        "device": {"arch": dev["arch"].split(":")[0], "compute_units": dev["compute_units"]},
+        "params": {k: int(full[k]) for k in ORDER},
+        "score_vs_defaults": round(best_s, 4),
+        "evaluations": nev,
+        "tuning_set": [{k: (list(map(list, v)) if k == "graphs" else (list(v) if k == "graph" else v))
+                        for k, v in it.items()} for it in TUNING_SET],
+        "defaults_ms": [round(x, 4) for x in base],
+        "tuned_ms": [round(x, 4) for x in tuned_ms],
+        "seconds": round(time.time() - t0, 1),
+        "command": "python -m paper_1508_03619_amd.autotune",
+    }
+    log(json.dumps(result))
+    if not args.dry_run:
+        path = args.out or tuned_path(dev["arch"], dev["compute_units"])
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(result, f, indent=1)
+            f.write("\n")
+        log(f"wrote {path}")
+
+
+if __name__ == "__main__":
+    main()

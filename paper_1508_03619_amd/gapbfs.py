@@ -75,6 +75,10 @@ def load():
         if not os.path.exists(_LIB_PATH):
             raise ImportError(f"{_LIB_PATH} is not built (run __graft_entry__.build() or "
                               "python -m paper_1508_03619_amd.build)")
+        # torch ships its own HIP runtime.  Loading torch first makes this
+        # library bind to that same runtime; loading the library first puts a
+        # second runtime in the process and one of the two then finds no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(_LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         i32p = ctypes.POINTER(ctypes.c_int32)
@@ -100,7 +104,55 @@ def load():
                      "gap_stream_copy"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
+        _apply_tuned(L)
         return L
+
+
+_defaults: dict = {}
+_tuned: Optional[tuple] = None
+
+
+def _apply_tuned(L):
+    """Remember the library's built-in parameters, then apply the tuned set
+    for this GPU model if one exists (``tuned/<arch>_<CUs>cu.json``, written
+    by ``autotune``).  GAPBFS_TUNED=0 keeps the built-in set."""
+    global _tuned
+    p = _Params()
+    if L.gap_get_params(ctypes.byref(p)) != GAP_OK:
+        raise GapError(GAP_EINTERNAL, "gap_get_params failed")
+    _defaults.update({k: int(getattr(p, k)) for k in PARAM_NAMES})
+    if os.environ.get("GAPBFS_TUNED", "1") == "0":
+        return
+    import torch
+    if not torch.cuda.is_available():
+        return
+    info = DeviceInfo()
+    if L.gap_device_query(ctypes.byref(info)) != GAP_OK:
+        return  # no device visible: nothing to tune for
+    from .autotune import read_tuned, tuned_path
+    path = tuned_path(info.arch.decode(), info.compute_units)
+    if not os.path.exists(path):
+        return
+    tuned = read_tuned(path)
+    for k, v in tuned.items():
+        if k not in PARAM_NAMES:
+            raise KeyError(f"{path}: unknown parameter {k}")
+        setattr(p, k, int(v))
+    if L.gap_set_params(ctypes.byref(p)) != GAP_OK:
+        raise GapError(GAP_EINVAL, f"{path}: {L.gap_last_error().decode()}")
+    _tuned = (path, dict(tuned))
+
+
+def library_defaults() -> dict:
+    """The library's built-in parameter set (before any tuned file)."""
+    load()
+    return dict(_defaults)
+
+
+def tuned_params() -> Optional[tuple]:
+    """(path, params) of the tuned file applied at load, or None."""
+    load()
+    return _tuned
 
 
 def _check(status: int):

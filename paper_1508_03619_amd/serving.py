@@ -381,6 +381,8 @@ def pool_edges(kind: str, size: int, seed: int):
         return inputs.rmat(size, 16, seed=seed)
     if kind == "grid":
         return inputs.grid(size, size, seed=seed)
+    if kind == "urand":
+        return inputs.urand_scale(size, 16, seed=seed)
     raise KeyError(kind)
 
 

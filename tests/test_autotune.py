@@ -1,0 +1,57 @@
+"""Autotuner host logic: the coordinate search, the per-model file naming and
+the validity of any committed tuned parameter file."""
+import glob
+import json
+import os
+
+import pytest
+
+from paper_1508_03619_amd import autotune as at
+
+
+def test_coordinate_descent_finds_separable_optimum():
+    space = {"a": [1, 2, 3, 4], "b": [10, 20, 30], "c": [0, 1]}
+    target = {"a": 3, "b": 10, "c": 1}
+    calls = []
+
+    def score(p):
+        calls.append(dict(p))
+        return 1.0 + sum((p[k] - target[k]) ** 2 for k in p)
+
+    best, s, nev = at.coordinate_descent(space, ["a", "b", "c"], {"a": 1, "b": 30, "c": 0}, score,
+                                         passes=3, log=lambda m: None)
+    assert best == target and s == pytest.approx(1.0)
+    assert nev == len({tuple(sorted(c.items())) for c in calls})  # evaluations are cached
+
+
+def test_coordinate_descent_ignores_noise_below_min_gain():
+    space = {"a": [1, 2, 3]}
+    best, _, _ = at.coordinate_descent(space, ["a"], {"a": 2}, lambda p: 1.0 - 0.001 * p["a"],
+                                       passes=2, min_gain=0.01, log=lambda m: None)
+    assert best == {"a": 2}
+
+
+def test_space_covers_order_and_names_are_library_parameters():
+    from paper_1508_03619_amd.gapbfs import PARAM_NAMES
+    assert set(at.ORDER) == set(at.SPACE)
+    assert set(at.SPACE) <= set(PARAM_NAMES)
+    assert all(v % 64 == 0 for v in at.SPACE["chunk_edges"])
+    assert set(at.SPACE["block"]) <= {256, 512, 1024}
+
+
+def test_tuned_path_per_model():
+    assert at.arch_key("gfx950:sramecc+:xnack-", 256) == "gfx950_256cu"
+    assert at.tuned_path("gfx950", 256).endswith(os.path.join("tuned", "gfx950_256cu.json"))
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(at.TUNED_DIR, "*.json"))))
+def test_committed_tuned_files_are_valid(path):
+    from paper_1508_03619_amd.gapbfs import PARAM_NAMES
+    params = at.read_tuned(path)
+    assert set(params) <= set(PARAM_NAMES)
+    for k, v in params.items():
+        if k in at.SPACE:
+            assert v in at.SPACE[k], (k, v)
+    with open(path) as f:
+        d = json.load(f)
+    assert os.path.basename(path) == at.arch_key(d["device"]["arch"], d["device"]["compute_units"]) + ".json"

@@ -1,0 +1,188 @@
+"""Parity at the measured sizes, in the launch configuration the benchmark
+times: R-MAT scale 22 and uniform-random 2^22 (single-source and the
+64-lane batch), the 4096^2 road-like grid (persistent kernel and captured
+level graphs), R-MAT scale 24 in batches of 64 and 256 lanes, and the mixed
+batch of 16 R-MAT graphs of scales 14-20.
+
+Sampled searches are checked in full against the oracle (depths bit-exact,
+parents valid, Section 2.1).  Every lane of a large batch is also checked
+for properties that hold at any size: parent[s] = s, depth[s] = 0, and the
+reached set has the size of the source's connected component, computed by
+the oracle's union-find."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpuutil import assert_valid, say
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def workload(name):
+    """(edge list, oracle adjacency or None, component labels, device graph)."""
+    if name not in _cache:
+        from paper_1508_03619_amd import inputs, gapbfs as gb
+        if name.startswith("mixed"):
+            raise KeyError(name)
+        say(f"{name}: generating")
+        el = inputs.workload(name)
+        say(f"{name}: building the device CSR")
+        g = gb.build_csr(el.n, el.src, el.dst)
+        _cache[name] = {"el": el, "g": g, "A": None, "cc": None}
+    return _cache[name]
+
+
+def adjacency(name):
+    w = workload(name)
+    if w["A"] is None:
+        say(f"{name}: oracle adjacency")
+        w["A"] = oracle.Adjacency(w["el"].n, w["el"].src, w["el"].dst)
+    return w["A"]
+
+
+def comp_sizes(name):
+    w = workload(name)
+    if w["cc"] is None:
+        say(f"{name}: oracle components")
+        lab = oracle.components(w["el"].n, w["el"].src, w["el"].dst)
+        w["cc"] = (lab, np.bincount(lab, minlength=w["el"].n))
+    return w["cc"]
+
+
+def drop(name):
+    w = _cache.pop(name, None)
+    if w is not None:
+        w["g"].free()
+
+
+def bench_sources(name, k=64):
+    from paper_1508_03619_amd import inputs
+    return [int(x) for x in inputs.pick_sources(workload(name)["el"], k, seed=inputs.SOURCE_SEEDS[name])]
+
+
+def run_single(g, s, params=None):
+    import torch
+    from paper_1508_03619_amd import gapbfs as gb
+    p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    gb.bfs(g, s, p, d, params=params)
+    torch.cuda.synchronize()
+    return p.cpu().numpy(), d.cpu().numpy()
+
+
+def check_batch_properties(name, lanes, P, D):
+    """Every lane: source entries and reached-set size (on the device)."""
+    import torch
+    lab, size = comp_sizes(name)
+    for i, s in enumerate(lanes):
+        assert int(P[i][s]) == s and int(D[i][s]) == 0, f"{name} lane {i}: source entries"
+        reached = int((D[i] >= 0).sum())
+        assert reached == int(size[lab[s]]), f"{name} lane {i}: reached {reached} != component {size[lab[s]]}"
+        assert int((P[i] >= 0).sum()) == reached, f"{name} lane {i}: parent/depth reach differ"
+        assert int(P[i].min()) >= -1 and int(D[i].min()) >= -1
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["rmat22", "urand22"])
+def test_fullsize_single_and_batch(gpu, name):
+    import torch
+    from paper_1508_03619_amd import gapbfs as gb
+    srcs = bench_sources(name)
+    g = workload(name)["g"]
+    A = adjacency(name)
+    for i in (0, 37):
+        say(f"{name}: single-source search {i} (source {srcs[i]}) vs oracle")
+        p, d = run_single(g, srcs[i])
+        assert_valid(A, srcs[i], p, d, what=name)
+    say(f"{name}: 64-lane batch")
+    P = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
+    D = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
+    gb.bfs_batch([g], [0] * 64, srcs, P, D)
+    torch.cuda.synchronize()
+    check_batch_properties(name, srcs, P, D)
+    for i in (5, 63):
+        say(f"{name}: batch lane {i} vs oracle")
+        assert_valid(A, srcs[i], P[i].cpu().numpy(), D[i].cpu().numpy(), what=f"{name} lane {i}")
+    del P, D
+    drop(name)
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_grid4096_persistent_and_graph(gpu):
+    name = "grid4096"
+    srcs = bench_sources(name, 2)
+    g = workload(name)["g"]
+    A = adjacency(name)
+    s = srcs[0]
+    ref = A.bfs(s)[0]
+    say(f"grid4096: source {s}, {int(ref.max())} levels")
+    for mode in (0, 2):
+        say(f"grid4096: mode {mode}")
+        p, d = run_single(g, s, params={"mode": mode})
+        assert_valid(A, s, p, d, ref, what=f"grid4096 mode {mode}")
+    drop(name)
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("lanes", [64, 256])
+def test_fullsize_rmat24_batch(gpu, lanes):
+    import torch
+    from paper_1508_03619_amd import gapbfs as gb
+    name = "rmat24"
+    srcs = bench_sources(name, lanes)
+    g = workload(name)["g"]
+    say(f"rmat24: batch of {lanes}")
+    P = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
+    D = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
+    gb.bfs_batch([g], [0] * lanes, srcs, P, D)
+    torch.cuda.synchronize()
+    say(f"rmat24: properties of {lanes} lanes")
+    check_batch_properties(name, srcs, P, D)
+    A = adjacency(name)
+    for i in (0, lanes - 1):
+        say(f"rmat24: lane {i} vs oracle")
+        assert_valid(A, srcs[i], P[i].cpu().numpy(), D[i].cpu().numpy(), what=f"rmat24 lane {i}")
+    del P, D
+    torch.cuda.empty_cache()
+    if lanes == 256:
+        drop(name)
+
+
+MIXED_SCALES = [14, 14, 15, 15, 16, 16, 17, 17, 18, 18, 19, 19, 20, 20, 20, 20]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("per_graph", [4, 16])
+def test_fullsize_mixed_batch(gpu, per_graph):
+    import torch
+    from paper_1508_03619_amd import inputs, gapbfs as gb
+    els = [inputs.rmat(s, 16, seed=30000 + i) for i, s in enumerate(MIXED_SCALES)]
+    graphs = [gb.build_csr(e.n, e.src, e.dst) for e in els]
+    gos, srcs = [], []
+    for gi, e in enumerate(els):
+        for s in inputs.pick_sources(e, per_graph, seed=1030000 + gi):
+            gos.append(gi)
+            srcs.append(int(s))
+    say(f"mixed: {len(srcs)} lanes over 16 graphs")
+    P = [torch.empty(graphs[gi].n, dtype=torch.int32, device="cuda") for gi in gos]
+    D = [torch.empty(graphs[gi].n, dtype=torch.int32, device="cuda") for gi in gos]
+    gb.bfs_batch(graphs, gos, srcs, P, D)
+    torch.cuda.synchronize()
+    done = set()
+    for i, (gi, s) in enumerate(zip(gos, srcs)):
+        if gi in done:
+            continue  # one lane per graph in full against the oracle
+        done.add(gi)
+        A = oracle.Adjacency(els[gi].n, els[gi].src, els[gi].dst)
+        assert_valid(A, s, P[i].cpu().numpy(), D[i].cpu().numpy(), what=f"mixed graph {gi} lane {i}")
+    for gi, e in enumerate(els):
+        lab = oracle.components(e.n, e.src, e.dst)
+        size = np.bincount(lab, minlength=e.n)
+        for i in [k for k in range(len(gos)) if gos[k] == gi]:
+            s = srcs[i]
+            assert int(D[i][s]) == 0 and int(P[i][s]) == s
+            assert int((D[i] >= 0).sum()) == int(size[lab[s]]), f"mixed graph {gi} lane {i}: reach"
+    for g in graphs:
+        g.free()
