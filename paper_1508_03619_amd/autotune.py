@@ -4,9 +4,9 @@ Section 2.3 allows one implementation and one set of tuning parameters for
 all input graphs.  This tuner therefore searches only hardware-facing
 parameters (direction-switch thresholds, workgroup size, hub splitting, the
 level schedule, the batched thresholds) on a fixed tuning set of graphs of
-the benchmark's three shapes at reduced size (R-MAT, uniform random,
-road-like grid, and a mixed multi-source batch), and writes the winner to
-``tuned/<arch>_<CUs>cu.json``.  The binding applies that file when it loads
+the benchmark's shapes at reduced size (R-MAT, uniform-random and road-like
+grid searches; R-MAT, uniform-random and mixed multi-source batches), and
+writes the winner to ``tuned/<arch>_<CUs>cu.json``.  The binding applies that file when it loads
 the library on a device of that model.  Parameters never change results:
 depths are unique and every schedule returns valid parents.
 
@@ -46,10 +46,11 @@ ORDER = ["block", "alpha", "beta", "hub_degree", "chunk_edges", "batch_alpha", "
 
 # Tuning set: the benchmark's graph shapes at reduced size, other seeds.
 TUNING_SET = [
-    {"kind": "single", "graph": ("rmat", 20, 7001), "sources": 8},
-    {"kind": "single", "graph": ("urand", 20, 7002), "sources": 8},
+    {"kind": "single", "graph": ("rmat", 21, 7001), "sources": 8},
+    {"kind": "single", "graph": ("urand", 21, 7002), "sources": 8},
     {"kind": "single", "graph": ("grid", 1024, 7003), "sources": 4},
-    {"kind": "batch", "graphs": [("rmat", 20, 7001)], "lanes": 64},
+    {"kind": "batch", "graphs": [("rmat", 21, 7001)], "lanes": 64},
+    {"kind": "batch", "graphs": [("urand", 21, 7002)], "lanes": 64},
     {"kind": "batch", "graphs": [("rmat", s, 7100 + s) for s in (14, 15, 16, 17, 18)], "lanes": 16},
 ]
 
