@@ -171,7 +171,11 @@ typedef struct gap_params {
   int32_t grid_split;    /* k >= 1: a persistent launch takes 1/k of the CUs
                             and at most k of them run at once (so searches
                             queued on different streams can overlap) */
-  int32_t reserved[3];
+  int32_t small_frontier; /* persistent single-source schedule: a top-down
+                            level whose frontier and frontier edges are both
+                            at most this runs on 16 workgroups while the
+                            rest wait (0 = every level on the whole grid) */
+  int32_t reserved[2];
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

@@ -144,6 +144,7 @@ static gap_params default_params() {
   p.batch_alpha = 8;
   p.batch_beta = 18;
   p.grid_split = 1;
+  p.small_frontier = 32768;
   return p;
 }
 
@@ -193,6 +194,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.grid_split < 1 || p.grid_split > 64) {
     set_error("params: grid_split must be in [1, 64]");
+    return GAP_EINVAL;
+  }
+  if (p.small_frontier < 0) {
+    set_error("params: small_frontier must be >= 0");
     return GAP_EINVAL;
   }
   if (p.batch_alpha < 1 || p.batch_beta < 1) {

@@ -30,6 +30,42 @@ struct SearchArgs {
 
 // ---- persistent cooperative kernel -------------------------------------------
 
+// Small levels: a top-down level whose frontier and frontier edges are both
+// at most p.small runs on the first kGroups workgroups only, which meet at a
+// barrier of their own (a barrier's cost grows with the number of arriving
+// workgroups, and such a level has too little work to need the whole grid).
+// The other workgroups park until the small group hands the search back:
+// the last arriver of each level's barrier decides whether the next level
+// is small and sends the answer with the release; when the small group
+// stops (a large level next, or the search done) it stores its state in
+// ctl->park and the level to rejoin at in ctl->resume.
+struct SmallDecision {
+  int64_t n, mu, nv, small_limit;
+  int32_t dir, d, have_bm, fsel_next;
+  Params p;
+  bool in_small, enabled;
+  __device__ BarrierDecision operator()(Ctl *ctl, const Totals &all) const {
+    const int64_t nv1 = (int64_t)all.nv, mf1 = (int64_t)all.mf;
+    int small_next = 0;
+    if (enabled && nv1 > 0 && nv1 <= small_limit && mf1 <= small_limit) {
+      const int32_t nd = decide_direction(dir, nv1, mf1, mu - mf1, nv, n, p, d + 1);
+      small_next = (nd == kTopDown);
+    }
+    if (in_small && !small_next) {
+      ParkState ps;
+      ps.level = d + 1;
+      ps.dir = dir;
+      ps.have_bm = have_bm;
+      ps.fsel = fsel_next;
+      ps.mu = mu;
+      ps.nf_prev = nv;
+      ctl->park = ps;
+      return {0, d + 1};
+    }
+    return {small_next, -1};
+  }
+};
+
 template <int BLOCK, bool STATS>
 __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   __shared__ Stage<BLOCK> st;
@@ -38,6 +74,8 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   const int64_t nwaves = nthreads / kWave;
   const int64_t gwave = tid / kWave;
   const unsigned int nblocks = gridDim.x;
+  const unsigned int nsmall = nblocks < (unsigned)kGroups ? nblocks : (unsigned)kGroups;
+  const bool small_enabled = a.p.small > 0 && nblocks > nsmall;
 
   init_vertices(a.g, a.parent, a.depth, a.source, tid, nthreads);
   Totals part = {};
@@ -48,6 +86,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   bool have_bm = false;
   int64_t mu = a.g.nnz, nf_prev = 0;
   int fsel = 0;
+  bool small = false;  // this level runs on the small group
   for (;;) {
     const Published &P = a.ctl->pub[d & 1];
     const int64_t nv = (int64_t)ld_agent(&P.t.nv);
@@ -84,14 +123,34 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     step_begin<BLOCK>(s, st);
     LaneAcc acc;
     if (dir == kTopDown)
-      td_step<BLOCK, STATS>(s, st, acc, gwave, nwaves);
+      td_step<BLOCK, STATS>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
     else
-      bu_step<BLOCK, STATS>(s, st, acc, gwave, nwaves);
+      bu_step<BLOCK, STATS>(s, st, acc, gwave, nwaves);  // never on the small group
     const Totals t = step_end<BLOCK>(s, st, acc);
-    if (!grid_sync(a.ctl, nblocks, t, (d + 1) & 1, (d + 1) & 1)) return;
-    if (dir == kBottomUp) fsel ^= 1;
+    const int fsel_next = (dir == kBottomUp) ? (fsel ^ 1) : fsel;
+    const SmallDecision dec{a.g.n, mu, nv, (int64_t)a.p.small, dir, d, have_bm ? 1 : 0, fsel_next,
+                            a.p, small, small_enabled};
+    int small_next = 0;
+    const BarrierSet bar = small ? small_barrier(a.ctl) : main_barrier(a.ctl);
+    if (!grid_sync_x(a.ctl, bar, small ? nsmall : nblocks, t, (d + 1) & 1, (d + 1) & 1, dec,
+                     small_next))
+      return;
+    fsel = fsel_next;
     nf_prev = nv;
     ++d;
+    if (small_next && !small && blockIdx.x >= nsmall) {
+      // park until the small group hands the search back
+      ParkState ps;
+      if (!park_wait(a.ctl, (unsigned int)d, ps)) return;
+      d = ps.level;
+      dir = ps.dir;
+      have_bm = ps.have_bm != 0;
+      fsel = ps.fsel;
+      mu = ps.mu;
+      nf_prev = ps.nf_prev;
+      continue;
+    }
+    small = small_next != 0;
   }
   fixup_parents(a.g.n, a.parent, tid, nthreads);
   if (tid == 0) a.ctl->levels = d;
@@ -402,7 +461,7 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
   a.bm1 = ws->bm[1];
   a.vbm = ws->bm[2];
   a.ctl = ws->ctl;
-  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges};
+  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier};
   a.recs = want_stats ? ws->recs : nullptr;
   a.max_recs = want_stats ? max_levels : 0;
 

@@ -59,11 +59,23 @@ struct alignas(128) Published {
   unsigned long long c[kGroups];
 };
 
+// Search state handed from the small group to the parked workgroups when
+// every workgroup rejoins (single-source persistent kernel).
+struct ParkState {
+  int level, dir, have_bm, fsel;
+  long long mu, nf_prev;
+};
+
 // Device-resident control block of one workspace (zeroed before a search).
 struct Ctl {
-  GroupSlot grp[kGroups];
+  GroupSlot grp[kGroups];    // barrier of the whole grid
   GroupSlot top;
   GenFlag gen[kGroups];
+  GroupSlot sgrp[kGroups];   // barrier of the small group (first kGroups workgroups)
+  GroupSlot stop;
+  GenFlag sgen[kGroups];
+  ParkState park;
+  unsigned int resume;       // level at which parked workgroups rejoin
   SegCount seg[2][kGroups];  // live append counters, per queue buffer set
   Published pub[2];          // frontier of level d lives in pub[d & 1]
   int err;                   // GAP_ETIMEOUT / GAP_EINTERNAL
@@ -78,6 +90,7 @@ struct Ctl {
 
 struct Params {
   int32_t alpha, beta, direction, hub, chunk;
+  int32_t small;  // top-down levels with |F| and m_f at most this run on kGroups workgroups
 };
 
 enum Dir : int32_t { kTopDown = 1, kBottomUp = 2 };
@@ -200,26 +213,50 @@ __device__ inline Totals take_totals(GroupSlot &s) {
   return t;
 }
 
-// Grid-wide barrier with a reduction, for a cooperative launch.  Every
-// workgroup calls it the same number of times, with its partial totals in
-// thread 0.  Arrival is two-level (workgroup -> its group -> top) so that no
-// address sees more than ~nblocks/kGroups atomics (same-address atomics
-// serialise).  The last workgroup of each group folds the group's totals
-// into the top slot and, when `publish` >= 0, publishes its group's queue
-// segment sizes of buffer set `bs`; the last group publishes the totals and
-// releases everyone with one release fence and plain flag stores (a release
-// store per flag would write the L2 back once per flag).
+// The counters and flags of one barrier: the whole grid's or the small
+// group's.
+struct BarrierSet {
+  GroupSlot *grp;
+  GroupSlot *top;
+  GenFlag *gen;
+};
+__device__ inline BarrierSet main_barrier(Ctl *c) { return {c->grp, &c->top, c->gen}; }
+__device__ inline BarrierSet small_barrier(Ctl *c) { return {c->sgrp, &c->stop, c->sgen}; }
+
+// What the last arriver decides for everyone: a flag delivered with the
+// release (bit 0 of the generation word) and, when resume >= 0, a value
+// stored to ctl->resume after the release fence.
+struct BarrierDecision {
+  int flag;
+  int resume;
+};
+struct NoDecision {
+  __device__ BarrierDecision operator()(Ctl *, const Totals &) const { return {0, -1}; }
+};
+
+// Grid-wide barrier with a reduction.  Every participating workgroup calls
+// it the same number of times, with its partial totals in thread 0.
+// Arrival is two-level (workgroup -> its group -> top) so that no address
+// sees more than ~nblocks/kGroups atomics (same-address atomics serialise).
+// The last workgroup of each group folds the group's totals into the top
+// slot and, when `publish` >= 0, publishes its group's queue segment sizes
+// of buffer set `bs`; the last group publishes the totals, runs `decide` on
+// them, and releases everyone with one release fence and plain flag stores
+// (a release store per flag would write the L2 back once per flag).  The
+// generation word advances by 2 and carries the decision's flag in bit 0;
+// `flag` returns it to every participant.
 // Bounded: a workgroup that waits longer than the timeout records
 // GAP_ETIMEOUT in ctl->err.  Returns false once an error has been recorded.
-__device__ inline bool grid_sync(Ctl *ctl, unsigned int nblocks, const Totals &part, int publish,
-                                 int bs) {
+template <class Decide>
+__device__ inline bool grid_sync_x(Ctl *ctl, BarrierSet B, unsigned int nblocks, const Totals &part,
+                                   int publish, int bs, const Decide &decide, int &flag) {
   __syncthreads();
-  __shared__ int s_ok;
+  __shared__ int s_ok, s_flag;
   if (threadIdx.x == 0) {
-    int ok = 1;
+    int ok = 1, fl = 0;
     const int g = (int)(blockIdx.x % kGroups);
-    const unsigned int gen0 = ld_agent(&ctl->gen[g].gen);
-    GroupSlot &gs = ctl->grp[g];
+    const unsigned int gen0 = ld_agent(&B.gen[g].gen);
+    GroupSlot &gs = B.grp[g];
     add_totals(gs, part);
     const unsigned int a =
         __hip_atomic_fetch_add(&gs.arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -229,27 +266,32 @@ __device__ inline bool grid_sync(Ctl *ctl, unsigned int nblocks, const Totals &p
       const Totals t = take_totals(gs);
       if (publish >= 0) publish_segment(ctl, publish, bs, g);
       st_agent(&gs.arrive, 0u);
-      add_totals(ctl->top, t);
+      add_totals(*B.top, t);
       const int ngroups = nblocks < (unsigned)kGroups ? (int)nblocks : kGroups;
-      const unsigned int b = __hip_atomic_fetch_add(&ctl->top.arrive, 1u, __ATOMIC_ACQ_REL,
+      const unsigned int b = __hip_atomic_fetch_add(&B.top->arrive, 1u, __ATOMIC_ACQ_REL,
                                                     __HIP_MEMORY_SCOPE_AGENT);
       if ((int)b == ngroups - 1) {
-        // last overall: publish the totals, clear, release every group
-        const Totals all = take_totals(ctl->top);
-        st_agent(&ctl->top.arrive, 0u);
+        // last overall: publish the totals, decide, clear, release every group
+        const Totals all = take_totals(*B.top);
+        st_agent(&B.top->arrive, 0u);
         if (publish >= 0) {
           publish_totals(ctl, publish, all);
           // groups without workgroups (nblocks < kGroups) publish empty segments
           for (int h = ngroups; h < kGroups; ++h) publish_segment(ctl, publish, bs, h);
         }
+        const BarrierDecision dd = decide(ctl, all);
+        fl = dd.flag & 1;
+        const unsigned int next = (((gen0 >> 1) + 1u) << 1) | (unsigned)fl;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        for (int h = 0; h < kGroups; ++h) st_agent(&ctl->gen[h].gen, gen0 + 1u);
+        if (dd.resume >= 0) st_agent(&ctl->resume, (unsigned int)dd.resume);
+        for (int h = 0; h < kGroups; ++h) st_agent(&B.gen[h].gen, next);
         released = true;
       }
     }
     if (!released) {
       const uint64_t t0 = rt_clock();
-      while (ld_agent(&ctl->gen[g].gen) == gen0) {
+      unsigned int v;
+      while ((v = ld_agent(&B.gen[g].gen)) == gen0) {
         __builtin_amdgcn_s_sleep(1);
         if (rt_clock() - t0 > kBarrierTimeoutTicks) {
           __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
@@ -258,12 +300,52 @@ __device__ inline bool grid_sync(Ctl *ctl, unsigned int nblocks, const Totals &p
           break;
         }
       }
+      fl = (int)(v & 1u);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     s_ok = ok;
+    s_flag = fl;
   }
   __syncthreads();
+  flag = s_flag;
+  return s_ok != 0;
+}
+
+__device__ inline bool grid_sync(Ctl *ctl, unsigned int nblocks, const Totals &part, int publish,
+                                 int bs) {
+  int flag;
+  return grid_sync_x(ctl, main_barrier(ctl), nblocks, part, publish, bs, NoDecision{}, flag);
+}
+
+// A parked workgroup waits until the small group sets ctl->resume above
+// `level` (bounded like the barrier), then takes over the handed-on state.
+constexpr uint64_t kParkTimeoutTicks = 3000000000ull;  // ~30 s at 100 MHz
+
+__device__ inline bool park_wait(Ctl *ctl, unsigned int level, ParkState &ps) {
+  __syncthreads();
+  __shared__ int s_ok;
+  __shared__ ParkState s_ps;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint64_t t0 = rt_clock();
+    while (ld_agent(&ctl->resume) <= level) {
+      __builtin_amdgcn_s_sleep(32);
+      if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          rt_clock() - t0 > kParkTimeoutTicks) {
+        __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    s_ps = ctl->park;
+    s_ok = ok;
+  }
+  __syncthreads();
+  ps = s_ps;
   return s_ok != 0;
 }
 

@@ -37,7 +37,8 @@ class _Params(ctypes.Structure):
                 ("hub_degree", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
                 ("graph_chunk", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
                 ("batch_alpha", ctypes.c_int32), ("batch_beta", ctypes.c_int32),
-                ("grid_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("grid_split", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_ if f[0] != "reserved"]

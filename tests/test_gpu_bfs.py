@@ -11,7 +11,8 @@ from tests.gpuutil import assert_valid, device_bfs, graph_pair, say
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [dict(mode=m, direction=d) for m in (0, 1, 2) for d in (0, 1, 2)]
+SCHEDULES = [dict(mode=m, direction=d) for m in (0, 1, 2) for d in (0, 1, 2)] + \
+    [dict(mode=0, direction=d, small_frontier=sf) for d in (0, 1) for sf in (0, 1 << 30)]
 
 
 def small_cases():
@@ -213,6 +214,25 @@ def test_grid_split_streams_overlap(gpu, split):
         gpu.set_params(**saved)
     for src, p, d in outs:
         assert_valid(A, src, p.cpu().numpy(), d.cpu().numpy(), what=f"split={split}")
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_small_group_levels(gpu, block):
+    """Levels handed to the small group and back: thresholds that keep every
+    top-down level small, none, and ones that switch several times."""
+    from paper_1508_03619_amd import inputs
+    for el, what in [(inputs.rmat(14, 16, seed=45), "rmat14"), (inputs.grid(300, 200, seed=46), "grid"),
+                     (inputs.urand(20000, 60000, seed=47), "urand")]:
+        g, A = graph_pair(gpu, el.n, el.src, el.dst)
+        for src in inputs.pick_sources(el, 2, seed=48):
+            ref = A.bfs(int(src))[0]
+            for sf in (0, 16, 64, 700, 5000, 1 << 30):
+                for direction in (0, 1):
+                    say(f"small group {what} block={block} small={sf} dir={direction}")
+                    parent, depth = device_bfs(gpu, g, int(src), params=dict(
+                        block=block, small_frontier=sf, direction=direction))
+                    assert_valid(A, int(src), parent, depth, ref, what=f"{what} small={sf}")
+        g.free()
 
 
 def test_grid_road_like(gpu):
