@@ -191,6 +191,8 @@ typedef struct gap_level_stat {
   int64_t claimed;      /* |F_{d+1}| */
   int64_t scanned;      /* adjacency entries read by the step */
   int64_t unvisited;    /* bottom-up: vertices still searching a parent */
+  int64_t time_ns;      /* device time from the level's start to the end of
+                           its barrier (real-time clock, 10 ns resolution) */
 } gap_level_stat;
 
 /*

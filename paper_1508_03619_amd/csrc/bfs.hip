@@ -95,12 +95,14 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
       a.recs[d - 1].claimed = (unsigned long long)nv;
       a.recs[d - 1].scanned = ld_agent(&P.t.scanned);
       a.recs[d - 1].unvisited = ld_agent(&P.t.unvisited);
+      a.recs[d - 1].t_end = rt_clock();
     }
     if (nv == 0) break;
     if (d > a.g.n) {  // more levels than vertices: inconsistent counters
       if (tid == 0) atomicExch(&a.ctl->err, (int)GAP_EINTERNAL);
       return;
     }
+    const unsigned long long level_t0 = STATS ? rt_clock() : 0ull;
     mu -= mf;
     const int32_t ndir = decide_direction(dir, nv, mf, mu, nf_prev, a.g.n, a.p, d);
     if (ndir == kBottomUp && !(dir == kBottomUp && have_bm)) {
@@ -116,6 +118,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
       r.direction = dir;
       r.frontier = (unsigned long long)nv;
       r.frontier_edges = (unsigned long long)mf;
+      r.t_start = level_t0;
       a.recs[d] = r;
     }
     StepArgs s{a.g, a.parent, a.depth, a.Q, d & 1, a.ctl, (fsel ? a.bm1 : a.bm0), a.vbm, (fsel ? a.bm0 : a.bm1),
@@ -216,6 +219,7 @@ __global__ __launch_bounds__(64) void k_dd_publish(DDArgs *A) {
     a.recs[L].claimed = t.nv;
     a.recs[L].scanned = t.scanned;
     a.recs[L].unvisited = t.unvisited;
+    a.recs[L].t_end = rt_clock();
   }
   if (L >= 0 && ctl->dir == kBottomUp) A->fsel ^= 1;
   const int64_t nv = (int64_t)t.nv, mf = (int64_t)t.mf;
@@ -243,6 +247,7 @@ __global__ __launch_bounds__(64) void k_dd_publish(DDArgs *A) {
     r.direction = ndir;
     r.frontier = (unsigned long long)nv;
     r.frontier_edges = (unsigned long long)mf;
+    r.t_start = rt_clock();
     a.recs[d] = r;
   }
 }
@@ -503,6 +508,9 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
       stats[i].claimed = (int64_t)recs[i].claimed;
       stats[i].scanned = (int64_t)recs[i].scanned;
       stats[i].unvisited = (int64_t)recs[i].unvisited;
+      stats[i].time_ns = recs[i].t_end > recs[i].t_start
+                             ? (int64_t)((recs[i].t_end - recs[i].t_start) * 10ull)
+                             : 0;
     }
   }
   if (num_levels) *num_levels = levels;

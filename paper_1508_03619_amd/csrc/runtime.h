@@ -52,6 +52,7 @@ gap_status device_info(int dev, const DeviceInfo **out);
 struct DevLevelRec {
   int32_t level, direction;
   unsigned long long frontier, frontier_edges, claimed, scanned, unvisited;
+  unsigned long long t_start, t_end;  // device real-time clock (100 MHz ticks)
 };
 
 // Scratch for searches queued on one (device, stream).  Reused by calls in

@@ -48,7 +48,7 @@ class LevelStat(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("direction", ctypes.c_int32),
                 ("frontier", ctypes.c_int64), ("frontier_edges", ctypes.c_int64),
                 ("claimed", ctypes.c_int64), ("scanned", ctypes.c_int64),
-                ("unvisited", ctypes.c_int64)]
+                ("unvisited", ctypes.c_int64), ("time_ns", ctypes.c_int64)]
 
 
 class DeviceInfo(ctypes.Structure):
