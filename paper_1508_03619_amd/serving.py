@@ -134,23 +134,78 @@ class Scheduler:
 # ---------------------------------------------------------------------------
 # serving loop
 
-def serve(ex, sched: Scheduler, queries: Sequence[Query],
-          on_done: Optional[Callable] = None) -> List[Query]:
-    """Run every query to completion.  ``queries`` are sorted by arrival on
-    the executor's clock (seconds from the start of the call)."""
-    queries = sorted(queries, key=lambda q: (q.arrival, q.qid))
-    nq = len(queries)
-    i = 0
+class OpenArrivals:
+    """Queries that arrive at preset times (open loop)."""
+
+    def __init__(self, queries: Sequence[Query]):
+        self.q = sorted(queries, key=lambda q: (q.arrival, q.qid))
+        self.i = 0
+
+    def due(self, now: float) -> List[Query]:
+        out = []
+        while self.i < len(self.q) and self.q[self.i].arrival <= now:
+            out.append(self.q[self.i])
+            self.i += 1
+        return out
+
+    def completed(self, q: Query, now: float) -> None:
+        pass
+
+    def next_time(self) -> Optional[float]:
+        return self.q[self.i].arrival if self.i < len(self.q) else None
+
+    @property
+    def exhausted(self) -> bool:
+        return self.i >= len(self.q)
+
+
+class ClosedArrivals:
+    """``clients`` clients, each sending its next query the moment its
+    previous one completes, ``total`` queries in all (closed loop).
+    ``make(k)`` builds query k; its arrival time is set on release."""
+
+    def __init__(self, clients: int, total: int, make: Callable[[int], Query]):
+        self.make = make
+        self.total = total
+        self.sent = 0
+        self.ready: List[float] = [0.0] * min(clients, total)
+
+    def due(self, now: float) -> List[Query]:
+        out = []
+        while self.ready and self.sent < self.total:
+            self.ready.pop()
+            q = self.make(self.sent)
+            q.arrival = now
+            self.sent += 1
+            out.append(q)
+        return out
+
+    def completed(self, q: Query, now: float) -> None:
+        if self.sent < self.total:
+            self.ready.append(now)
+
+    def next_time(self) -> Optional[float]:
+        return None
+
+    @property
+    def exhausted(self) -> bool:
+        return self.sent >= self.total
+
+
+def serve(ex, sched: Scheduler, queries, on_done: Optional[Callable] = None) -> List[Query]:
+    """Run every query to completion.  ``queries`` is a list of queries with
+    arrival times on the executor's clock (seconds from the start of the
+    call), or an arrival source (OpenArrivals / ClosedArrivals)."""
+    src = queries if hasattr(queries, "due") else OpenArrivals(queries)
     inflight: Dict[int, List[Query]] = {}
     free = list(range(ex.slots))[::-1]
     finished: List[Query] = []
     ex.start()
-    while i < nq or sched.pending or inflight:
+    while not src.exhausted or sched.pending or inflight:
         progressed = False
         now = ex.now()
-        while i < nq and queries[i].arrival <= now:
-            sched.submit(queries[i])
-            i += 1
+        for q in src.due(now):
+            sched.submit(q)
             progressed = True
         for slot in list(inflight):
             if ex.poll(slot):
@@ -164,6 +219,8 @@ def serve(ex, sched: Scheduler, queries: Sequence[Query],
                 sched.release(batch)
                 free.append(slot)
                 finished.extend(batch)
+                for q in batch:
+                    src.completed(q, t)
                 progressed = True
         while free:
             batch = sched.take_batch()
@@ -178,7 +235,7 @@ def serve(ex, sched: Scheduler, queries: Sequence[Query],
             inflight[slot] = batch
             progressed = True
         if not progressed:
-            ex.idle(queries[i].arrival if i < nq else None)
+            ex.idle(src.next_time())
     return finished
 
 
@@ -280,29 +337,95 @@ class SimExecutor:
         self.t = max(self.t, min(cands))
 
 
+CALIBRATION_LANES = (8, 64)
+
+
+def prefer_batch(lanes: int, t_single: float, t_batch: Dict[int, float]) -> bool:
+    """True when one multi-source launch of ``lanes`` queries is expected to
+    finish sooner than ``lanes`` single-source searches in a row.  The batch
+    time is interpolated linearly in the lane count between the calibrated
+    points (and held flat below the first)."""
+    if lanes <= 1:
+        return False
+    pts = sorted(t_batch.items())
+    if lanes <= pts[0][0]:
+        tb = pts[0][1]
+    elif lanes >= pts[-1][0]:
+        tb = pts[-1][1] * lanes / pts[-1][0]
+    else:
+        tb = pts[-1][1]
+        for (l0, t0), (l1, t1) in zip(pts, pts[1:]):
+            if l0 <= lanes <= l1:
+                tb = t0 + (t1 - t0) * (lanes - l0) / (l1 - l0)
+                break
+    return tb < lanes * t_single
+
+
 class GpuExecutor:
     """Runs batches through the library on ``slots`` HIP streams.
 
-    A batch of at least ``min_batch_lanes`` queries is one multi-source
-    launch; a smaller one is that many single-source searches queued on the
-    slot's stream.  Outputs are allocated on the slot's stream when the
-    batch is launched and released when the host retires it.
+    Each launch slot has its own stream; with grid_split = slots every
+    persistent launch takes 1/slots of the compute units, so launches on
+    different slots overlap.  A batch of queries on one graph runs either as
+    one multi-source launch or as single-source searches in a row on the
+    slot's stream, whichever the graph's calibration (``calibrate``) says is
+    faster.  Outputs are allocated on the slot's stream when the batch is
+    launched and released when the host retires it.
     """
 
-    def __init__(self, graphs: Sequence, slots: int = 4, min_batch_lanes: int = 8):
+    def __init__(self, graphs: Sequence, slots: int = 8, sources: Optional[Sequence] = None):
         import torch
         from . import gapbfs as gb
         self.torch = torch
         self.gb = gb
         self.graphs = list(graphs)
         self.slots = int(slots)
-        self.min_batch_lanes = int(min_batch_lanes)
         self._saved_params = gb.get_params()
         gb.set_params(grid_split=self.slots)
         self.streams = [torch.cuda.Stream() for _ in range(self.slots)]
         self.events = [torch.cuda.Event() for _ in range(self.slots)]
         self.out: Dict[int, tuple] = {}
         self.t0 = 0.0
+        self.launch_kinds = collections.Counter()
+        # per graph: single-search time and batch times (ms); unknown -> batch
+        self.t_single: List[float] = [math.inf] * len(self.graphs)
+        self.t_batch: List[Dict[int, float]] = [{1: 0.0} for _ in self.graphs]
+        if sources is not None:
+            self.calibrate(sources)
+
+    def calibrate(self, sources: Sequence[np.ndarray], reps: int = 2):
+        """Time one single-source search and batches of CALIBRATION_LANES
+        lanes on every graph, on one slot (the share of the device a launch
+        gets while serving)."""
+        torch, gb = self.torch, self.gb
+        st = self.streams[0]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+        def timed(fn):
+            with torch.cuda.stream(st):
+                fn()
+                best = math.inf
+                for _ in range(reps):
+                    e0.record(st)
+                    fn()
+                    e1.record(st)
+                    e1.synchronize()
+                    best = min(best, e0.elapsed_time(e1))
+            return best
+
+        for gi, g in enumerate(self.graphs):
+            cand = sources[gi]
+            L = max(CALIBRATION_LANES)
+            srcs = [int(cand[(k * 7919) % len(cand)]) for k in range(L)]
+            with torch.cuda.stream(st):
+                ps = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(L)]
+                ds = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(L)]
+            self.t_single[gi] = timed(lambda: gb.bfs(g, srcs[0], ps[0], ds[0], stream=st))
+            self.t_batch[gi] = {l: timed(lambda l=l: gb.bfs_batch([g], [0] * l, srcs[:l], ps[:l], ds[:l],
+                                                                  stream=st))
+                                for l in CALIBRATION_LANES}
+            del ps, ds
+        torch.cuda.synchronize()
 
     def start(self):
         self.torch.cuda.synchronize()
@@ -318,9 +441,12 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             ps = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in batch]
             ds = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in batch]
-            if len(batch) >= self.min_batch_lanes:
+            gi = batch[0].graph
+            if prefer_batch(len(batch), self.t_single[gi], self.t_batch[gi]):
                 gb.bfs_batch([g], [0] * len(batch), [q.source for q in batch], ps, ds, stream=st)
+                self.launch_kinds["batch"] += 1
             else:
+                self.launch_kinds["single"] += len(batch)
                 for q, p, d in zip(batch, ps, ds):
                     gb.bfs(g, q.source, p, d, stream=st)
             self.events[slot].record(st)

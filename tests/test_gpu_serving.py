@@ -28,14 +28,14 @@ def test_serving_mix_equals_alone(gpu):
 
     say(f"serving {len(qs)} queries over {len(pool.graphs)} graphs, 4 slots")
     sched = sv.Scheduler(pool.sizes, budget_bytes=1 << 28, max_lanes=64)
-    ex = sv.GpuExecutor(pool.graphs, slots=4, min_batch_lanes=4)
+    ex = sv.GpuExecutor(pool.graphs, slots=4, sources=pool.sources)
     try:
         done = sv.serve(ex, sched, qs, on_done)
     finally:
         ex.close()
     assert sorted(q.qid for q in done) == list(range(300))
-    sizes = [q.batch_size for q in done]
-    assert max(sizes) >= 4 and min(sizes) < 4, "both launch kinds must be exercised"
+    assert ex.launch_kinds["batch"] > 0 and ex.launch_kinds["single"] > 0, \
+        f"both launch kinds must be exercised: {dict(ex.launch_kinds)}"
     say("serving: checking each query alone")
     refs = {}
     p1 = {}

@@ -132,3 +132,39 @@ def test_workspace_bound_matches_layout():
     assert sv.batch_workspace_bytes(n, 64) == 664 * n
     assert sv.batch_workspace_bytes(n, 65) == (48 + 1024 + 128) * n
     assert sv.batch_workspace_bytes(n, 300) == 2 * (96 + 2048 + 128) * n
+
+
+def test_prefer_batch_cost_model():
+    # level-bound graph: a batch costs about one search -> batch from 2 lanes
+    assert sv.prefer_batch(2, 10.0, {8: 12.0, 64: 20.0})
+    # cheap singles, costly batches -> singles until the batch amortises
+    tb = {8: 2.5, 64: 8.0}
+    assert not sv.prefer_batch(4, 0.33, tb)
+    assert not sv.prefer_batch(7, 0.33, tb)
+    assert sv.prefer_batch(40, 0.33, tb)
+    assert not sv.prefer_batch(1, 100.0, tb)       # one query: always a single search
+    # interpolation between the calibrated points, extrapolation above
+    assert sv.prefer_batch(36, 5.25 / 36 + 1e-3, tb)
+    assert not sv.prefer_batch(36, 5.25 / 36 - 1e-3, tb)
+    assert sv.prefer_batch(128, 16.0 / 128 + 1e-3, tb)
+    assert not sv.prefer_batch(128, 16.0 / 128 - 1e-3, tb)
+
+
+def test_closed_loop_keeps_client_count_in_flight():
+    sizes = [1000, 2000]
+    cands = [np.arange(n, dtype=np.int32) for n in sizes]
+    pool = sv.poisson_queries(0.0, 300, cands, seed=3)
+    sched = sv.Scheduler(sizes, budget_bytes=1 << 30, max_lanes=8)
+    ex = sv.SimExecutor(2, linear_service, sizes)
+    src = sv.ClosedArrivals(16, 300, lambda k: pool[k])
+    done = sv.serve(ex, sched, src)
+    assert sorted(q.qid for q in done) == list(range(300))
+    # at every arrival after the first 16, exactly one query had just completed
+    events = sorted([(q.arrival, 1) for q in done] + [(q.done, -1) for q in done])
+    level, peak = 0, 0
+    for _, dlt in events:
+        level += dlt
+        peak = max(peak, level)
+    assert peak <= 16
+    arrivals = sorted(q.arrival for q in done)
+    assert arrivals[:16] == [0.0] * 16 and arrivals[16] > 0.0
