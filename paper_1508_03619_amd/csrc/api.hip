@@ -110,6 +110,23 @@ gap_status coop_end(int dev, hipStream_t s, CoopOrder *o) {
   return GAP_OK;
 }
 
+// Private (scratch) bytes per lane of a kernel, cached.  A kernel that
+// spills may have fewer waves resident than its occupancy says (scratch is
+// granted per wave), so an ordinary launch cannot rely on residency.
+static size_t kernel_scratch(const void *kern) {
+  static std::mutex mu;
+  static std::map<const void *, size_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(kern);
+  if (it != cache.end()) return it->second;
+  hipFuncAttributes attr{};
+  size_t bytes = 1;  // unknown: treat as spilling
+  if (hipFuncGetAttributes(&attr, kern) == hipSuccess) bytes = attr.localSizeBytes;
+  (void)hipGetLastError();
+  cache.emplace(kern, bytes);
+  return bytes;
+}
+
 gap_status launch_resident(const void *kern, int max_grid, int block, void **kargs, int split,
                            const DeviceInfo *di, hipStream_t s, int *grid_out) {
   int grid = max_grid;
@@ -118,8 +135,11 @@ gap_status launch_resident(const void *kern, int max_grid, int block, void **kar
     grid = max_grid / split / x * x;
     if (grid < x) grid = max_grid / split;
     if (grid < 1) grid = 1;
+  }
+  if (split > 1 && kernel_scratch(kern) == 0) {
     GAP_HIP(hipLaunchKernel(kern, dim3(grid), dim3(block), kargs, 0, s));
   } else {
+    // the runtime checks residency (and such launches do not overlap)
     GAP_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), kargs, 0, s));
   }
   if (grid_out) *grid_out = grid;
@@ -275,7 +295,10 @@ gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const
   if (e == hipSuccess) e = hipMalloc(&ws->dd_args, kArgsBytes);
   if (e == hipSuccess) e = hipHostMalloc(&ws->h_flags, 4 * sizeof(int));
   if (e == hipSuccess) e = hipHostMalloc(&ws->h_args, kArgsBytes);
-  if (e == hipSuccess) e = hipMemset(ws->ctl, 0, sizeof(Ctl));
+  // on the workspace's stream: a null-stream memset is not ordered before
+  // work on a non-blocking stream
+  if (e == hipSuccess) e = hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), ws->stream);
+
   if (e != hipSuccess) {
     release_single(ws);
     return hip_fail(e, "workspace allocation");

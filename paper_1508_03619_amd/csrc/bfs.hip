@@ -72,7 +72,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
   const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int64_t nwaves = nthreads / kWave;
-  const int64_t gwave = tid / kWave;
+  const int64_t gwave = uni(tid / kWave);
   const unsigned int nblocks = gridDim.x;
   const unsigned int nsmall = nblocks < (unsigned)kGroups ? nblocks : (unsigned)kGroups;
   const bool small_enabled = a.p.small > 0 && nblocks > nsmall;
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   bool small = false;  // this level runs on the small group
   for (;;) {
     const Published &P = a.ctl->pub[d & 1];
-    const int64_t nv = (int64_t)ld_agent(&P.t.nv);
-    const int64_t mf = (int64_t)ld_agent(&P.t.mf);
+    const int64_t nv = uni((int64_t)ld_agent(&P.t.nv));
+    const int64_t mf = uni((int64_t)ld_agent(&P.t.mf));
     if (STATS && tid == 0 && d > 0 && d - 1 < a.max_recs) {
       a.recs[d - 1].claimed = (unsigned long long)nv;
       a.recs[d - 1].scanned = ld_agent(&P.t.scanned);
@@ -138,6 +138,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     if (!grid_sync_x(a.ctl, bar, small ? nsmall : nblocks, t, (d + 1) & 1, (d + 1) & 1, dec,
                      small_next))
       return;
+    small_next = uni(small_next);
     fsel = fsel_next;
     nf_prev = nv;
     ++d;
@@ -145,12 +146,12 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
       // park until the small group hands the search back
       ParkState ps;
       if (!park_wait(a.ctl, (unsigned int)d, ps)) return;
-      d = ps.level;
-      dir = ps.dir;
-      have_bm = ps.have_bm != 0;
-      fsel = ps.fsel;
-      mu = ps.mu;
-      nf_prev = ps.nf_prev;
+      d = uni(ps.level);
+      dir = uni(ps.dir);
+      have_bm = uni(ps.have_bm) != 0;
+      fsel = uni(ps.fsel);
+      mu = uni((int64_t)ps.mu);
+      nf_prev = uni((int64_t)ps.nf_prev);
       continue;
     }
     small = small_next != 0;

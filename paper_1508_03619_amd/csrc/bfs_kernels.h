@@ -191,9 +191,17 @@ __device__ inline void step_begin(const StepArgs &a, Stage<BLOCK> &st) {
 // workgroup's totals into thread 0.
 template <int BLOCK>
 __device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc) {
-  const unsigned long long s0 = wave_sum_u64(acc.mf), s1 = wave_sum_u64(acc.nv);
-  const unsigned long long s2 = wave_sum_u64(acc.scanned), s3 = wave_sum_u64(acc.unvisited);
   const int wv = threadIdx.x / kWave;
+  // a wave that counted nothing (most waves of a small level) skips the
+  // cross-lane reductions
+  const bool any = __ballot((acc.mf | acc.nv | acc.scanned | acc.unvisited) != 0ull) != 0ull;
+  unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  if (any) {
+    s0 = wave_sum_u64(acc.mf);
+    s1 = wave_sum_u64(acc.nv);
+    s2 = wave_sum_u64(acc.scanned);
+    s3 = wave_sum_u64(acc.unvisited);
+  }
   if (lane_id() == 0) {
     st.part[wv][0] = s0;
     st.part[wv][1] = s1;
@@ -215,13 +223,13 @@ __device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &
   int2 *cdst = a.Q.cs(bs_out) + g * a.Q.ccap + (int64_t)st.cbase;
   for (unsigned int i = threadIdx.x; i < nc; i += BLOCK) cdst[i] = st.c[i];
   Totals t = {};
-  if (threadIdx.x == 0) {
-    for (int w = 0; w < BLOCK / kWave; ++w) {
-      t.mf += st.part[w][0];
-      t.nv += st.part[w][1];
-      t.scanned += st.part[w][2];
-      t.unvisited += st.part[w][3];
-    }
+  if (threadIdx.x < kWave) {  // wave 0 folds the per-wave partials, one lane per wave
+    const int l = threadIdx.x;
+    const bool has = l < BLOCK / kWave;
+    t.mf = wave_sum_u64(has ? st.part[l][0] : 0ull);
+    t.nv = wave_sum_u64(has ? st.part[l][1] : 0ull);
+    t.scanned = wave_sum_u64(has ? st.part[l][2] : 0ull);
+    t.unvisited = wave_sum_u64(has ? st.part[l][3] : 0ull);
   }
   acc = LaneAcc();
   return t;
@@ -353,7 +361,9 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
   const int64_t nwords = (a.g.n + kWave - 1) / kWave;
   for (int64_t base = gwave * J; base < nwords; base += nwaves * J) {
     uint64_t vis[J];
-    int64_t e[J], end[J];
+    int64_t e[J];       // next adjacency entry
+    int32_t rem[J];     // entries left (a degree fits in 31 bits)
+    int32_t degv[J];
     int32_t pu[J];
     bool act[J];
 #pragma unroll
@@ -363,24 +373,22 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
       const int64_t v = (base + j) * kWave + lane;
       act[j] = ((vis[j] >> lane) & 1ull) == 0ull;
       e[j] = 0;
-      end[j] = 0;
+      rem[j] = 0;
       pu[j] = -1;
       if (act[j]) {
         e[j] = a.g.row_ptr[v];
-        end[j] = a.g.row_ptr[v + 1];
+        rem[j] = (int32_t)(a.g.row_ptr[v + 1] - e[j]);
         if (STATS) acc.unvisited += 1;
       }
+      degv[j] = rem[j];
     }
-    int64_t degv[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) degv[j] = end[j] - e[j];
     bool any = true;
     while (any) {
       int32_t u[J][R];
 #pragma unroll
       for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int k = 0; k < R; ++k) u[j][k] = (act[j] && e[j] + k < end[j]) ? a.g.col[e[j] + k] : -1;
+        for (int k = 0; k < R; ++k) u[j][k] = (act[j] && k < rem[j]) ? a.g.col[e[j] + k] : -1;
       bool hit[J][R];
 #pragma unroll
       for (int j = 0; j < J; ++j)
@@ -396,14 +404,15 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
         for (int k = R - 1; k >= 0; --k)
           if (hit[j][k]) pu[j] = u[j][k];
         if (STATS) {  // entries up to and including the first hit
-          for (int k = 0; k < R && e[j] + k < end[j]; ++k) {
+          for (int k = 0; k < R && k < rem[j]; ++k) {
             ++used;
             if (hit[j][k]) break;
           }
           acc.scanned += used;
         }
         e[j] += R;
-        if (pu[j] >= 0 || e[j] >= end[j])
+        rem[j] -= R;
+        if (pu[j] >= 0 || rem[j] <= 0)
           act[j] = false;
         else
           more = true;
@@ -423,7 +432,7 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
         a.nbm[base + j] = b;
         if (b) a.vbm[base + j] = vis[j] | b;
       }
-      stage_append<BLOCK>(a, st, found, (int32_t)v, degv[j], acc);
+      stage_append<BLOCK>(a, st, found, (int32_t)v, (int64_t)degv[j], acc);
     }
   }
 }

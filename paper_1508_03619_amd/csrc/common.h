@@ -148,6 +148,17 @@ __host__ __device__ inline void swap_ptr(T &a, T &b) {
 
 __device__ inline int first_lane(uint64_t mask) { return __builtin_ctzll(mask); }
 
+// A value that is the same in every lane, moved to a scalar register (the
+// compiler cannot prove that a loaded value is wave-uniform; keeping loop
+// state in SGPRs leaves the VGPRs to the steps).
+__device__ inline int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)x); }
+__device__ inline int64_t uni(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Real-time clock (100 MHz constant clock on CDNA).
 __device__ inline uint64_t rt_clock() { return __builtin_amdgcn_s_memrealtime(); }
 

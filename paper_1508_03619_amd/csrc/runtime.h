@@ -109,8 +109,10 @@ gap_status coop_end(int dev, hipStream_t s, CoopOrder *o);
 // split = k > 1: an ordinary launch of max_grid / k workgroups rounded down
 // to a multiple of the die count, so each die receives the same number;
 // with at most k such grids in flight (coop_begin) their sum fits on every
-// die at once.  Waits inside the kernels are bounded, so a broken residency
-// assumption ends in GAP_ETIMEOUT rather than a hang.
+// die at once.  A kernel that uses scratch is still launched cooperatively
+// (its waves may be limited by scratch, not by occupancy).  Waits inside
+// the kernels are bounded, so a broken residency assumption ends in
+// GAP_ETIMEOUT rather than a hang.
 gap_status launch_resident(const void *kern, int max_grid, int block, void **kargs, int split,
                            const DeviceInfo *di, hipStream_t s, int *grid_out);
 
