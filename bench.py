@@ -79,6 +79,22 @@ class GraphCase:
             f"built in {time.time() - t0:.1f}s")
 
 
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken from the current kernel sources; else None."""
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{kernel}_rmat22_urand22.txt")
+    if not os.path.exists(tpath):
+        return None
+    from paper_1508_03619_amd.rocprof_summary import kernel_source_hash
+    try:
+        tj = json.load(open(tpath))
+        if tj.get("source_hash") == kernel_source_hash():
+            return int(tj.get("bytes_per_launch"))
+    except (OSError, ValueError, TypeError):
+        pass
+    return None
+
+
 def component_edges(g, el):
     """Per-vertex count of undirected edges in its connected component
     (m_s of a search from that vertex), from the device CSR's degrees and
@@ -310,6 +326,13 @@ def main():
             for s in c.sources:
                 gb.bfs(c.g, int(s), c.parent, c.depth)
         torch.cuda.synchronize()
+        for c in cases:  # one 64-lane batch per graph (the batched kernel's counters)
+            ns = len(c.sources)
+            ps = [torch.empty(c.g.n, dtype=torch.int32, device="cuda") for _ in range(ns)]
+            ds = [torch.empty(c.g.n, dtype=torch.int32, device="cuda") for _ in range(ns)]
+            gb.bfs_batch([c.g], [0] * ns, [int(s) for s in c.sources], ps, ds)
+            torch.cuda.synchronize()
+            del ps, ds
         log("profile leg done")
         return
 
@@ -383,17 +406,7 @@ def main():
     avg_alg_bytes = alg_sum / launches
     achieved = avg_alg_bytes / (avg_launch_ms * 1e-3) / 1e9
 
-    # HBM traffic from committed rocprofv3 counter runs, if they match this build.
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_k_bfs_persistent_rmat22_urand22.txt")
-    if os.path.exists(tpath):
-        from paper_1508_03619_amd.rocprof_summary import kernel_source_hash
-        try:
-            tj = json.load(open(tpath))
-            if tj.get("source_hash") == kernel_source_hash():
-                traffic = int(tj.get("bytes_per_launch"))
-        except Exception:
-            traffic = None
+    traffic = committed_traffic("k_bfs_persistent")
 
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -437,6 +450,16 @@ def main():
             detail[c.name]["single64_ms_sum"] = round(single_ms, 3)
             detail[c.name]["batch_speedup_vs_single"] = round(single_ms / bt, 2)
             del parents, depths
+        # counted HBM traffic of the batched kernel (committed counter run over
+        # the same two 64-lane batches) against the measured batch times
+        bt_mean = float(np.mean([detail[c.name]["batch64_ms"] for c in cases]))
+        btraffic = committed_traffic("k_msbfs")
+        detail["batch_roofline"] = {
+            "kernel": "k_msbfs", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "avg_launch_ms": round(bt_mean, 3), "traffic": btraffic,
+            "achieved_counted": (round(btraffic / (bt_mean * 1e-3) / 1e9, 1) if btraffic else None),
+            "frac_counted": (round(btraffic / (bt_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                             if btraffic else None)}
 
     legs = set(args.legs.split(",")) if args.legs else set()
     if "all" in legs:

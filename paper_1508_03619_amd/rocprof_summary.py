@@ -4,6 +4,8 @@ Usage:
   python -m paper_1508_03619_amd.rocprof_summary stats <kernel_stats.csv> <out.txt> --cmd "<command>"
   python -m paper_1508_03619_amd.rocprof_summary traffic <fetch_counter_collection.csv>
          <write_counter_collection.csv> <out.json> --kernel k_bfs_persistent --copy-bytes N --cmd "..."
+  python -m paper_1508_03619_amd.rocprof_summary counters <counter_collection.csv>... --out <out.txt>
+         --kernel k_bfs_persistent --kernel k_msbfs --cmd "..."
 
 The traffic summary scales the counters of the search kernel by the ratio
 (known bytes / counted bytes) measured on the streaming-copy kernel in the
@@ -96,6 +98,35 @@ def traffic(args):
     print(json.dumps(res, indent=1))
 
 
+def counters(args):
+    """Average of every collected counter per dispatch of each kernel, and
+    the L2 hit rate where TCC_HIT_sum and TCC_MISS_sum were collected."""
+    per = {}  # kernel -> counter -> [per-dispatch values]
+    for path in args.csv:
+        rows = list(csv.DictReader(open(path)))
+        names = sorted({r["Counter_Name"] for r in rows})
+        for c in names:
+            for k, vals in _counter_per_dispatch(path, c).items():
+                per.setdefault(k, {})[c] = vals
+    lines = ["# rocprofv3 counters, average per dispatch", f"# command: {args.cmd}",
+             f"# kernel-source hash: {kernel_source_hash()}", ""]
+    for want in args.kernel:
+        ks = [k for k in per if want in k]
+        for k in ks:
+            lines.append(f"{k}")
+            cs = per[k]
+            for c in sorted(cs):
+                v = cs[c]
+                lines.append(f"  {c:28s} {sum(v) / len(v):16.1f}   ({len(v)} dispatches)")
+            if "TCC_HIT_sum" in cs and "TCC_MISS_sum" in cs:
+                h = sum(cs["TCC_HIT_sum"]) / len(cs["TCC_HIT_sum"])
+                m = sum(cs["TCC_MISS_sum"]) / len(cs["TCC_MISS_sum"])
+                lines.append(f"  {'L2 hit rate':28s} {h / max(h + m, 1.0):16.3f}")
+            lines.append("")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -110,8 +141,13 @@ def main():
     t.add_argument("--kernel", default="k_bfs_persistent")
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--cmd", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--out", required=True)
+    c.add_argument("--kernel", action="append", default=[])
+    c.add_argument("--cmd", default="")
     a = ap.parse_args()
-    stats(a) if a.what == "stats" else traffic(a)
+    {"stats": stats, "traffic": traffic, "counters": counters}[a.what](a)
 
 
 if __name__ == "__main__":
