@@ -296,9 +296,8 @@ def main():
                          "source, no timing and no JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(each search runs on a single MI355X; see the sharding notes in the design).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(each search runs on a single MI355X).", file=sys.stderr)
         sys.exit(2)
 
     import torch
