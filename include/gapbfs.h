@@ -175,7 +175,10 @@ typedef struct gap_params {
                             level whose frontier and frontier edges are both
                             at most this runs on 16 workgroups while the
                             rest wait (0 = every level on the whole grid) */
-  int32_t reserved[2];
+  int32_t lds_bitmap;    /* persistent single-source schedule: 1 = bottom-up
+                            steps copy the frontier bitmap (n/8 bytes) into
+                            each workgroup's LDS when it fits, 0 = never */
+  int32_t reserved[1];
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

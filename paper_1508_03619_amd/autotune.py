@@ -41,9 +41,10 @@ SPACE: Dict[str, List[int]] = {
     "batch_alpha": [2, 4, 8, 15, 30],
     "batch_beta": [6, 12, 18, 36, 72],
     "small_frontier": [0, 4096, 16384, 32768, 131072],
+    "lds_bitmap": [0, 1],
 }
-ORDER = ["block", "alpha", "beta", "hub_degree", "chunk_edges", "small_frontier", "batch_alpha",
-         "batch_beta", "mode", "graph_chunk"]
+ORDER = ["block", "alpha", "beta", "hub_degree", "chunk_edges", "small_frontier", "lds_bitmap",
+         "batch_alpha", "batch_beta", "mode", "graph_chunk"]
 
 # Tuning set: the benchmark's graph shapes at reduced size, other seeds.
 TUNING_SET = [

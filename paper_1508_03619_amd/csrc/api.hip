@@ -46,6 +46,7 @@ gap_status device_info(int dev, const DeviceInfo **out) {
     di.device = dev;
     di.cus = prop.multiProcessorCount;
     di.lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    di.lds_per_block = (int)prop.sharedMemPerBlock;
     di.l2_bytes = prop.l2CacheSize;
     di.clock_khz = prop.clockRate;
     di.total_mem = prop.totalGlobalMem;
@@ -127,8 +128,8 @@ static size_t kernel_scratch(const void *kern) {
   return bytes;
 }
 
-gap_status launch_resident(const void *kern, int max_grid, int block, void **kargs, int split,
-                           const DeviceInfo *di, hipStream_t s, int *grid_out) {
+gap_status launch_resident(const void *kern, int max_grid, int block, size_t shmem, void **kargs,
+                           int split, const DeviceInfo *di, hipStream_t s, int *grid_out) {
   int grid = max_grid;
   if (split > 1) {
     const int x = di->xccs;
@@ -137,10 +138,10 @@ gap_status launch_resident(const void *kern, int max_grid, int block, void **kar
     if (grid < 1) grid = 1;
   }
   if (split > 1 && kernel_scratch(kern) == 0) {
-    GAP_HIP(hipLaunchKernel(kern, dim3(grid), dim3(block), kargs, 0, s));
+    GAP_HIP(hipLaunchKernel(kern, dim3(grid), dim3(block), kargs, shmem, s));
   } else {
     // the runtime checks residency (and such launches do not overlap)
-    GAP_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), kargs, 0, s));
+    GAP_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), kargs, (unsigned int)shmem, s));
   }
   if (grid_out) *grid_out = grid;
   return GAP_OK;
@@ -165,6 +166,7 @@ static gap_params default_params() {
   p.batch_beta = 18;
   p.grid_split = 1;
   p.small_frontier = 32768;
+  p.lds_bitmap = 1;
   return p;
 }
 
@@ -214,6 +216,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.grid_split < 1 || p.grid_split > 64) {
     set_error("params: grid_split must be in [1, 64]");
+    return GAP_EINVAL;
+  }
+  if (p.lds_bitmap != 0 && p.lds_bitmap != 1) {
+    set_error("params: lds_bitmap must be 0 or 1");
     return GAP_EINVAL;
   }
   if (p.small_frontier < 0) {

@@ -26,6 +26,7 @@ struct SearchArgs {
   Params p;
   DevLevelRec *recs;
   int32_t max_recs;
+  int32_t lds_bm;  // 1: the frontier bitmap fits the dynamic LDS of each workgroup
 };
 
 // ---- persistent cooperative kernel -------------------------------------------
@@ -69,6 +70,7 @@ struct SmallDecision {
 template <int BLOCK, bool STATS>
 __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   __shared__ Stage<BLOCK> st;
+  extern __shared__ uint64_t lds_fbm[];  // frontier bitmap copy (lds_bm)
   const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
   const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int64_t nwaves = nthreads / kWave;
@@ -128,7 +130,8 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     if (dir == kTopDown)
       td_step<BLOCK, STATS>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
     else
-      bu_step<BLOCK, STATS>(s, st, acc, gwave, nwaves);  // never on the small group
+      bu_step<BLOCK, STATS>(s, st, acc, gwave, nwaves,  // never on the small group
+                            a.lds_bm ? lds_fbm : nullptr);
     const Totals t = step_end<BLOCK>(s, st, acc);
     const int fsel_next = (dir == kBottomUp) ? (fsel ^ 1) : fsel;
     const SmallDecision dec{a.g.n, mu, nv, (int64_t)a.p.small, dir, d, have_bm ? 1 : 0, fsel_next,
@@ -293,28 +296,47 @@ __global__ __launch_bounds__(kLevelBlock) void k_dd_fixup(DDArgs *A) {
 
 template <int BLOCK, bool STATS>
 static gap_status launch_persistent(const SearchArgs &a, const DeviceInfo *di, int blocks_per_cu,
-                                    int split, hipStream_t stream) {
+                                    int split, int lds_bitmap, hipStream_t stream) {
   auto kern = k_bfs_persistent<BLOCK, STATS>;
+  SearchArgs args = a;
+  // the frontier bitmap goes to LDS when it fits next to the static staging
+  size_t shmem = 0;
+  args.lds_bm = 0;
+  if (lds_bitmap) {
+    hipFuncAttributes attr{};
+    const size_t bytes = sizeof(uint64_t) * (size_t)((a.g.n + kWave - 1) / kWave);
+    if (hipFuncGetAttributes(&attr, (const void *)kern) == hipSuccess &&
+        attr.sharedSizeBytes + bytes + 1024 <= (size_t)di->lds_per_block) {
+      shmem = bytes;
+      args.lds_bm = 1;
+    }
+    (void)hipGetLastError();
+  }
   int per_cu = 0;
-  GAP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
+  GAP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, shmem));
   if (per_cu < 1) {
     set_error("persistent kernel does not fit on a compute unit");
     return GAP_EDEVICE;
   }
   if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
-  SearchArgs args = a;
   void *kargs[] = {&args};
-  return launch_resident((const void *)kern, per_cu * di->cus, BLOCK, kargs, split, di, stream,
-                         nullptr);
+  return launch_resident((const void *)kern, per_cu * di->cus, BLOCK, shmem, kargs, split, di,
+                         stream, nullptr);
 }
 
 template <bool STATS>
 static gap_status dispatch_persistent(const SearchArgs &a, const DeviceInfo *di,
                                       const gap_params &p, hipStream_t stream) {
   switch (p.block) {
-    case 256: return launch_persistent<256, STATS>(a, di, p.blocks_per_cu, p.grid_split, stream);
-    case 512: return launch_persistent<512, STATS>(a, di, p.blocks_per_cu, p.grid_split, stream);
-    default: return launch_persistent<1024, STATS>(a, di, p.blocks_per_cu, p.grid_split, stream);
+    case 256:
+      return launch_persistent<256, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.lds_bitmap,
+                                           stream);
+    case 512:
+      return launch_persistent<512, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.lds_bitmap,
+                                           stream);
+    default:
+      return launch_persistent<1024, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.lds_bitmap,
+                                            stream);
   }
 }
 

@@ -354,11 +354,18 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
 #ifndef GAP_BU_ROUND
 #define GAP_BU_ROUND 4
 #endif
+// lfbm: when not NULL, LDS room for the whole frontier bitmap; the step
+// first copies F_d there and probes LDS instead of the L2-held copy.
 template <int BLOCK, bool STATS, int J = GAP_BU_WORDS, int R = GAP_BU_ROUND>
 __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
-                        int64_t nwaves) {
+                        int64_t nwaves, uint64_t *lfbm = nullptr) {
   const int lane = lane_id();
   const int64_t nwords = (a.g.n + kWave - 1) / kWave;
+  if (lfbm) {
+    for (int64_t i = threadIdx.x; i < nwords; i += BLOCK) lfbm[i] = a.fbm[i];
+    __syncthreads();
+  }
+  const uint64_t *fb = lfbm ? lfbm : a.fbm;
   for (int64_t base = gwave * J; base < nwords; base += nwaves * J) {
     uint64_t vis[J];
     int64_t e[J];       // next adjacency entry
@@ -394,7 +401,7 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
       for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int k = 0; k < R; ++k)
-          hit[j][k] = u[j][k] >= 0 && ((a.fbm[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
+          hit[j][k] = u[j][k] >= 0 && ((fb[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
       bool more = false;
 #pragma unroll
       for (int j = 0; j < J; ++j) {

@@ -594,7 +594,7 @@ static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int split, in
   MsArgs args = a;
   void *kargs[] = {&args};
   // 1024-thread workgroups, one per CU
-  gap_status st = launch_resident((const void *)kern, di->cus, kMsBlock, kargs, split, di, stream,
+  gap_status st = launch_resident((const void *)kern, di->cus, kMsBlock, 0, kargs, split, di, stream,
                                   nullptr);
   if (st != GAP_OK) return st;
   int64_t blocks = (ntiles + kOutBlock / kWave - 1) / (kOutBlock / kWave);

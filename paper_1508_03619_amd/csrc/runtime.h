@@ -38,6 +38,7 @@ struct DeviceInfo {
   int device = -1;
   int cus = 0;
   int lds_per_cu = 0;
+  int lds_per_block = 0;
   int l2_bytes = 0;
   int clock_khz = 0;
   size_t total_mem = 0;
@@ -113,8 +114,8 @@ gap_status coop_end(int dev, hipStream_t s, CoopOrder *o);
 // (its waves may be limited by scratch, not by occupancy).  Waits inside
 // the kernels are bounded, so a broken residency assumption ends in
 // GAP_ETIMEOUT rather than a hang.
-gap_status launch_resident(const void *kern, int max_grid, int block, void **kargs, int split,
-                           const DeviceInfo *di, hipStream_t s, int *grid_out);
+gap_status launch_resident(const void *kern, int max_grid, int block, size_t shmem, void **kargs,
+                           int split, const DeviceInfo *di, hipStream_t s, int *grid_out);
 
 gap_params params_current();
 gap_status params_check(const gap_params &p);

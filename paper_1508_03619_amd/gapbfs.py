@@ -38,7 +38,7 @@ class _Params(ctypes.Structure):
                 ("graph_chunk", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
                 ("batch_alpha", ctypes.c_int32), ("batch_beta", ctypes.c_int32),
                 ("grid_split", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("lds_bitmap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_ if f[0] != "reserved"]
