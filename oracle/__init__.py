@@ -61,6 +61,8 @@ def _bind(path: str):
     i64p = ctypes.POINTER(ctypes.c_int64)
     lib.oracle_build_adjacency.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i64p, i32p]
     lib.oracle_build_adjacency.restype = ctypes.c_int64
+    lib.oracle_build_out_adjacency.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i64p, i32p]
+    lib.oracle_build_out_adjacency.restype = ctypes.c_int64
     lib.oracle_bfs.argtypes = [ctypes.c_int64, i64p, i32p, ctypes.c_int32, i32p, i32p]
     lib.oracle_bfs.restype = ctypes.c_int64
     lib.oracle_check.argtypes = [ctypes.c_int64, i64p, i32p, ctypes.c_int32, i32p, i32p, i32p, i64p]
@@ -88,17 +90,20 @@ def _i64(a):
 
 
 class Adjacency:
-    """Symmetrised, cleaned adjacency built by the oracle from raw pairs."""
+    """Cleaned adjacency built by the oracle from raw pairs: symmetrised
+    (undirected, the default) or out-lists only (``directed=True``)."""
 
-    def __init__(self, n: int, src: np.ndarray, dst: np.ndarray, _lib=None):
+    def __init__(self, n: int, src: np.ndarray, dst: np.ndarray, _lib=None, directed: bool = False):
         L = _lib or lib()
         src = np.ascontiguousarray(src, dtype=np.int32)
         dst = np.ascontiguousarray(dst, dtype=np.int32)
         m = int(src.shape[0])
         self.n = int(n)
+        self.directed = bool(directed)
         self.offsets = np.zeros(self.n + 1, dtype=np.int64)
         adj = np.empty(max(2 * m, 1), dtype=np.int32)
-        nnz = L.oracle_build_adjacency(self.n, m, _i32(src), _i32(dst), _i64(self.offsets), _i32(adj))
+        build = L.oracle_build_out_adjacency if self.directed else L.oracle_build_adjacency
+        nnz = build(self.n, m, _i32(src), _i32(dst), _i64(self.offsets), _i32(adj))
         if nnz < 0:
             raise ValueError("oracle_build_adjacency: bad input")
         self.adj = adj[:nnz].copy()

@@ -15,8 +15,9 @@
  * depths from a trivial serial search show each parent one level above its
  * child.
  * Graph clean-up (paper, Section 2.3): removing duplicate edges and
- * self-loops and reordering neighbours are legal; the benchmark graphs here
- * are undirected, so every raw pair is inserted in both directions.
+ * self-loops and reordering neighbours are legal.  Undirected graphs insert
+ * every raw pair in both directions; directed graphs (Section 2.2: some of
+ * the paper's inputs are directed) keep each pair's direction.
  *
  * Pins (tests): exhaustive small graphs against Floyd-Warshall and boolean
  * matrix powers, random graphs against scipy's csgraph, closed forms (path,
@@ -76,6 +77,49 @@ int64_t oracle_build_adjacency(int64_t n, int64_t m, const int32_t *src,
     int64_t row_begin = out;
     for (int64_t i = start; i < end; ++i) {
       if (i > start && adj[i] == adj[i - 1]) continue;
+      adj[out++] = adj[i];
+    }
+    offsets[v] = row_begin;
+    start = end;
+  }
+  offsets[n] = out;
+  return out;
+}
+
+/*
+ * Directed variant: out-lists only (u -> v for every raw pair (u, v),
+ * u != v), sorted and duplicate-free.  A search over these lists follows
+ * edges in their direction; the validator's edge test (is v in the list of
+ * parent[v]?) then checks the directed edge parent[v] -> v.
+ *   adj: caller-provided int32[m] (upper bound, compacted in place)
+ */
+int64_t oracle_build_out_adjacency(int64_t n, int64_t m, const int32_t *src,
+                                   const int32_t *dst, int64_t *offsets,
+                                   int32_t *adj) {
+  if (n < 0 || m < 0 || !offsets || (m > 0 && (!src || !dst || !adj)))
+    return -1;
+  for (int64_t v = 0; v <= n; ++v) offsets[v] = 0;
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= n || v >= n) return -1;
+    if (u != v) offsets[u + 1] += 1;
+  }
+  for (int64_t v = 0; v < n; ++v) offsets[v + 1] += offsets[v];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!fill) return -1;
+  for (int64_t v = 0; v < n; ++v) fill[v] = offsets[v];
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u != v) adj[fill[u]++] = v;
+  }
+  free(fill);
+  int64_t out = 0, start = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t end = offsets[v + 1];
+    if (end - start > 1) qsort(adj + start, (size_t)(end - start), sizeof(int32_t), cmp_i32);
+    int64_t row_begin = out;
+    for (int64_t i = start; i < end; ++i) {
+      if (i > start && adj[i] == adj[i - 1]) continue;  /* repeated pair */
       adj[out++] = adj[i];
     }
     offsets[v] = row_begin;

@@ -26,6 +26,19 @@ MUTANTS = {
     "unionfind_no_union": ("        label[rb] = ra;", "        label[rb] = rb;"),
 }
 
+# Mistakes in the directed builder (several edits each), caught by the
+# directed pins.
+D_COUNT = "    if (u != v) offsets[u + 1] += 1;\n"
+D_FILL = "    if (u != v) adj[fill[u]++] = v;\n"
+DIRECTED_MUTANTS = {
+    "directed_reversed": [(D_COUNT, "    if (u != v) offsets[v + 1] += 1;\n"),
+                          (D_FILL, "    if (u != v) adj[fill[v]++] = u;\n")],
+    "directed_symmetrised": [(D_COUNT, "    if (u != v) { offsets[u + 1] += 1; offsets[v + 1] += 1; }\n"),
+                             (D_FILL, "    if (u != v) { adj[fill[u]++] = v; adj[fill[v]++] = u; }\n")],
+    "directed_keeps_self_loops": [(D_COUNT, "    offsets[u + 1] += 1;\n"),
+                                  (D_FILL, "    adj[fill[u]++] = v;\n")],
+}
+
 
 def pins_pass(L):
     from paper_1508_03619_amd import inputs
@@ -43,6 +56,30 @@ def pins_pass(L):
 
 def test_unmutated_oracle_passes_the_pins(oracle_lib):
     assert pins_pass(oracle_lib)
+
+
+def _compile_mutant(tmp_path, edits):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
+    for old, new in edits:
+        assert src.count(old) >= 1, f"mutation anchor missing: {old!r}"
+        src = src.replace(old, new, 1)
+    csrc = tmp_path / "oracle_mut.c"
+    csrc.write_text(src)
+    so = str(tmp_path / "liboracle_mut.so")
+    import subprocess
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-std=c11", "-o", so, str(csrc)], check=True)
+    return oracle._bind(so)
+
+
+@pytest.mark.parametrize("name", sorted(DIRECTED_MUTANTS))
+def test_directed_mutant_is_caught(tmp_path, name):
+    from tests import test_oracle_directed as TD
+    L = _compile_mutant(tmp_path, DIRECTED_MUTANTS[name])
+    try:
+        caught = not TD.directed_pins_ok(L)
+    except Exception:
+        caught = True
+    assert caught, f"mutant {name} passed every directed pin"
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
