@@ -51,37 +51,57 @@ typedef int32_t gap_status;
 /* Opaque, immutable graph resident in device memory (CSR). */
 typedef struct gap_graph gap_graph;
 
+/* gap_build_csr flag: keep edge directions (Section 2.1 allows directed
+ * graphs; a search then follows edges from tail to head only). */
+#define GAP_BUILD_DIRECTED 1u
+
 /*
- * gap_build_csr -- build the undirected graph used by every search
- * (Section 2.3: the graph is loaded and built once, untimed).
+ * gap_build_csr -- build the graph used by every search (Section 2.3: the
+ * graph is loaded and built once, untimed).
  *   num_vertices  n, 1 <= n <= 2^31 - 1
  *   num_edges     number of raw pairs, >= 0
  *   src, dst      host int32[num_edges], each value in [0, n); copied, the
  *                 caller keeps ownership and may free them on return
- *   flags         0 (reserved)
+ *   flags         0: undirected; GAP_BUILD_DIRECTED: the pair (src[i],
+ *                 dst[i]) is the edge src[i] -> dst[i]; no other bit is
+ *                 defined
  *   stream        stream used for the upload and build kernels
  *   out           receives the handle; release it with gap_free
- * Every pair is inserted in both directions, self-loops and duplicates are
- * removed, and each neighbour list is sorted ascending.  The result is an
- * int64 row_ptr[n+1] and an int32 col[nnz] in device memory owned by the
- * handle.  The call returns after the build has finished.
- * Errors: GAP_EINVAL (NULL out, n out of range, an ID out of range,
- * nnz >= 2^32 per call), GAP_ENOMEM, GAP_EDEVICE.
+ * Undirected: every pair is inserted in both directions.  Directed: the
+ * handle holds the out-lists and also the in-lists (the transpose, read by
+ * bottom-up steps), so it takes about twice the memory of one CSR.  In both
+ * cases self-loops and duplicates are removed and each list is sorted
+ * ascending; a CSR is an int64 row_ptr[n+1] and an int32 col[nnz] in device
+ * memory owned by the handle.  The call returns after the build has
+ * finished.
+ * Errors: GAP_EINVAL (NULL out, n out of range, an ID out of range, an
+ * unknown flag, more than 2^32 stored entries per call), GAP_ENOMEM,
+ * GAP_EDEVICE.
  */
 gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges,
                          const int32_t *src, const int32_t *dst,
                          uint32_t flags, void *stream, gap_graph **out);
 
-/* Vertex count n and stored (directed) adjacency entries nnz = 2|E|. */
+/* Vertex count n and stored adjacency entries nnz: 2|E| for an undirected
+ * graph, |E| (out-list entries) for a directed one. */
 gap_status gap_graph_info(const gap_graph *g, int64_t *n, int64_t *nnz);
 
+/* 1 if g was built with GAP_BUILD_DIRECTED, 0 if not, GAP_EINVAL for NULL. */
+gap_status gap_graph_directed(const gap_graph *g);
+
 /*
- * gap_graph_export -- copy the CSR to host memory (for cross-checks and
- * edge counting; not on the search path).  row_ptr: host int64[n+1];
- * col: host int32[nnz] (either may be NULL to skip it).  Synchronous.
+ * gap_graph_export -- copy the CSR (the out-lists of a directed graph) to
+ * host memory (for cross-checks and edge counting; not on the search
+ * path).  row_ptr: host int64[n+1]; col: host int32[nnz] (either may be
+ * NULL to skip it).  Synchronous.
  */
 gap_status gap_graph_export(const gap_graph *g, int64_t *row_ptr,
                             int32_t *col);
+
+/* As gap_graph_export, for the in-lists (the same arrays as the out-lists
+ * when the graph is undirected). */
+gap_status gap_graph_export_in(const gap_graph *g, int64_t *row_ptr,
+                               int32_t *col);
 
 /*
  * gap_bfs -- one direction-optimizing search (Section 2.1 output,
@@ -90,7 +110,8 @@ gap_status gap_graph_export(const gap_graph *g, int64_t *row_ptr,
  *   source   vertex in [0, n); a degree-0 source is legal and reaches only
  *            itself
  *   parent   device int32[n], written: parent[source] = source, -1 for
- *            unreachable vertices, otherwise a neighbour one level closer
+ *            unreachable vertices, otherwise a vertex one level closer
+ *            with an edge to this one (an in-neighbour when directed)
  *   depth    device int32[n] or NULL; written: hop distance, -1 when
  *            unreachable
  *   stream   queue for the work
@@ -122,8 +143,10 @@ gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent,
  *                     depths is not NULL and depths[i] is not NULL, at
  *                     depths[i]
  *   stream            queue for the work
+ * Undirected graphs only.
  * Errors: GAP_EINVAL (NULL arrays, counts <= 0, index or source out of
- * range, graphs on different devices), GAP_ENOMEM, GAP_EDEVICE.
+ * range, graphs on different devices, a directed graph), GAP_ENOMEM,
+ * GAP_EDEVICE.
  */
 gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          const int32_t *graph_of_source,

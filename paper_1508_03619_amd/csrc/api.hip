@@ -429,13 +429,14 @@ gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges, const int32_t 
     set_error("gap_build_csr: bad edge arrays");
     return GAP_EINVAL;
   }
-  if (flags != 0) {
-    set_error("gap_build_csr: flags must be 0");
+  if ((flags & ~GAP_BUILD_DIRECTED) != 0) {
+    set_error("gap_build_csr: unknown flag bits 0x%x", flags & ~GAP_BUILD_DIRECTED);
     return GAP_EINVAL;
   }
   gap_status st = require_device();
   if (st != GAP_OK) return st;
-  return build_csr(num_vertices, num_edges, src, dst, (hipStream_t)stream, out);
+  return build_csr(num_vertices, num_edges, src, dst, (flags & GAP_BUILD_DIRECTED) != 0,
+                   (hipStream_t)stream, out);
 }
 
 gap_status gap_graph_info(const gap_graph *g, int64_t *n, int64_t *nnz) {
@@ -448,18 +449,40 @@ gap_status gap_graph_info(const gap_graph *g, int64_t *n, int64_t *nnz) {
   return GAP_OK;
 }
 
-gap_status gap_graph_export(const gap_graph *g, int64_t *row_ptr, int32_t *col) {
+static gap_status export_csr(const gap_graph *g, const int64_t *d_row_ptr, const int32_t *d_col,
+                             int64_t nnz, int64_t *row_ptr, int32_t *col, const char *what) {
   if (!g) {
-    set_error("gap_graph_export: NULL graph");
+    set_error("%s: NULL graph", what);
     return GAP_EINVAL;
   }
   GAP_HIP(hipSetDevice(g->device));
   if (row_ptr)
-    GAP_HIP(hipMemcpy(row_ptr, g->row_ptr, sizeof(int64_t) * (size_t)(g->n + 1),
+    GAP_HIP(hipMemcpy(row_ptr, d_row_ptr, sizeof(int64_t) * (size_t)(g->n + 1),
                       hipMemcpyDeviceToHost));
-  if (col && g->nnz > 0)
-    GAP_HIP(hipMemcpy(col, g->col, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost));
+  if (col && nnz > 0)
+    GAP_HIP(hipMemcpy(col, d_col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
   return GAP_OK;
+}
+
+gap_status gap_graph_export(const gap_graph *g, int64_t *row_ptr, int32_t *col) {
+  clear_error();
+  return export_csr(g, g ? g->row_ptr : nullptr, g ? g->col : nullptr, g ? g->nnz : 0, row_ptr,
+                    col, "gap_graph_export");
+}
+
+gap_status gap_graph_export_in(const gap_graph *g, int64_t *row_ptr, int32_t *col) {
+  clear_error();
+  return export_csr(g, g ? g->row_ptr_in : nullptr, g ? g->col_in : nullptr, g ? g->nnz_in : 0,
+                    row_ptr, col, "gap_graph_export_in");
+}
+
+gap_status gap_graph_directed(const gap_graph *g) {
+  clear_error();
+  if (!g) {
+    set_error("gap_graph_directed: NULL graph");
+    return GAP_EINVAL;
+  }
+  return g->directed ? 1 : 0;
 }
 
 gap_status gap_bfs_ex(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
@@ -509,6 +532,10 @@ gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
       set_error("gap_bfs_batch: graphs on different devices");
       return GAP_EINVAL;
     }
+    if (graphs[i]->directed) {
+      set_error("gap_bfs_batch: graph %d is directed (batched searches take undirected graphs)", i);
+      return GAP_EINVAL;
+    }
   }
   for (int32_t i = 0; i < num_sources; ++i) {
     const int32_t gi = graph_of_source[i];
@@ -533,6 +560,8 @@ void gap_free(gap_graph *g) {
   if (!g) return;
   (void)hipSetDevice(g->device);
   (void)hipDeviceSynchronize();
+  if (g->row_ptr_in && g->row_ptr_in != g->row_ptr) (void)hipFree(g->row_ptr_in);
+  if (g->col_in && g->col_in != g->col) (void)hipFree(g->col_in);
   if (g->row_ptr) (void)hipFree(g->row_ptr);
   if (g->col) (void)hipFree(g->col);
   delete g;

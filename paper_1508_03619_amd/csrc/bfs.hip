@@ -475,7 +475,7 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
     if (st != GAP_OK) return st;
   }
   SearchArgs a{};
-  a.g = DevGraph{g->row_ptr, g->col, g->n, g->nnz};
+  a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->n, g->nnz, g->directed};
   a.parent = parent;
   a.depth = depth ? depth : ws->depth_scratch;
   a.source = source;

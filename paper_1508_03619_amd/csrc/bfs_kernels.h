@@ -383,8 +383,8 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
       rem[j] = 0;
       pu[j] = -1;
       if (act[j]) {
-        e[j] = a.g.row_ptr[v];
-        rem[j] = (int32_t)(a.g.row_ptr[v + 1] - e[j]);
+        e[j] = a.g.row_ptr_in[v];
+        rem[j] = (int32_t)(a.g.row_ptr_in[v + 1] - e[j]);
         if (STATS) acc.unvisited += 1;
       }
       degv[j] = rem[j];
@@ -395,7 +395,7 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
 #pragma unroll
       for (int j = 0; j < J; ++j)
 #pragma unroll
-        for (int k = 0; k < R; ++k) u[j][k] = (act[j] && k < rem[j]) ? a.g.col[e[j] + k] : -1;
+        for (int k = 0; k < R; ++k) u[j][k] = (act[j] && k < rem[j]) ? a.g.col_in[e[j] + k] : -1;
       bool hit[J][R];
 #pragma unroll
       for (int j = 0; j < J; ++j)
@@ -433,6 +433,9 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
       if (found) {
         a.parent[v] = pu[j];
         a.depth[v] = a.d + 1;
+        // the next frontier's edges are out-edges: on a directed graph the
+        // in-degree read above is not the count the top-down side needs
+        if (a.g.directed) degv[j] = (int32_t)(a.g.row_ptr[v + 1] - a.g.row_ptr[v]);
       }
       const uint64_t b = __ballot(found);
       if (base + j < nwords && lane == 0) {
@@ -445,8 +448,10 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
 }
 
 // Top-down -> bottom-up: build the frontier bitmap (depth == d) and the
-// visited bitmap (parent >= 0, isolated vertices and padding count as
-// visited so whole words can be skipped).
+// visited bitmap (parent >= 0; vertices that no edge enters and padding
+// count as visited so whole words can be skipped).  Undirected, "no edge
+// enters" is degree 0, which the parent encoding already holds; directed,
+// it is in-degree 0, read from the in-lists.
 __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *parent,
                                           const int32_t *depth, int32_t d, uint64_t *fbm,
                                           uint64_t *vbm, int64_t gwave, int64_t nwaves) {
@@ -457,7 +462,10 @@ __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *pare
     bool visited = true, front = false;
     if (v < g.n) {
       const int32_t p = parent[v];
-      visited = (p >= 0) || (p == kIsolated);
+      if (g.directed)
+        visited = (p >= 0) || (g.row_ptr_in[v + 1] == g.row_ptr_in[v]);
+      else
+        visited = (p >= 0) || (p == kIsolated);
       front = depth[v] == d;
     }
     const uint64_t bv = __ballot(visited);

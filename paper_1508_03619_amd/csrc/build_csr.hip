@@ -1,10 +1,12 @@
-// Graph build on the device (untimed, Section 2.3): symmetrise, drop
-// self-loops, sort, de-duplicate, and lay out as CSR with int64 offsets.
+// Graph build on the device (untimed, Section 2.3): drop self-loops, sort,
+// de-duplicate, and lay out as CSR with int64 offsets.
 //
-// Each raw pair (u, v), u != v, becomes the two keys (u << b) | v and
-// (v << b) | u with b = ceil(log2 n); one radix sort over 2b bits orders the
-// keys by (row, column), equal neighbours become adjacent and are dropped,
-// and the row offsets are read off the sorted keys.
+// Undirected: each raw pair (u, v), u != v, becomes the two keys
+// (u << b) | v and (v << b) | u with b = ceil(log2 n); one radix sort over
+// 2b bits orders the keys by (row, column), equal neighbours become
+// adjacent and are dropped, and the row offsets are read off the sorted
+// keys.  Directed: the same pipeline twice, once with the keys (u, v) (the
+// out-lists) and once with (v, u) (the in-lists, read by bottom-up steps).
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -14,8 +16,9 @@
 
 namespace gap {
 
+// mode 0: both directions (two keys per pair); 1: u -> v only; 2: v -> u only
 __global__ void k_make_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                            int64_t m, int64_t n, int bits, uint64_t sentinel,
+                            int64_t m, int64_t n, int bits, uint64_t sentinel, int mode,
                             uint64_t *__restrict__ keys, int *bad) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
@@ -27,8 +30,12 @@ __global__ void k_make_keys(const int32_t *__restrict__ src, const int32_t *__re
       k0 = ((uint64_t)u << bits) | (uint64_t)v;
       k1 = ((uint64_t)v << bits) | (uint64_t)u;
     }
-    keys[2 * e] = k0;
-    keys[2 * e + 1] = k1;
+    if (mode == 0) {
+      keys[2 * e] = k0;
+      keys[2 * e + 1] = k1;
+    } else {
+      keys[e] = mode == 1 ? k0 : k1;
+    }
   }
 }
 
@@ -103,40 +110,26 @@ struct DevBuf {
 };
 }  // namespace
 
-gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                     hipStream_t stream, gap_graph **out) {
-  int dev = 0;
-  GAP_HIP(hipGetDevice(&dev));
-  int bits = 1;
-  while (bits < 31 && (1ll << bits) < n) ++bits;
+// One CSR from the raw pairs on the device: keys of the chosen direction(s)
+// (mode as in k_make_keys), sort, drop repeats, scatter columns, offsets.
+// Allocates *row_ptr (int64[n+1]) and *col (int32[nnz]).
+static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, int64_t n, int64_t m,
+                           int bits, int mode, hipStream_t stream, int64_t **row_ptr_out,
+                           int32_t **col_out, int64_t *nnz_out, int64_t *maxdeg_out) {
   const uint64_t mask = (1ull << bits) - 1ull;
   const uint64_t sentinel = (1ull << (2 * bits)) - 1ull;  // = a self-loop key, never kept
-  const int64_t len = 2 * m;
-  if (len >= (1ll << 32)) {
-    set_error("gap_build_csr: more than 2^32 directed entries in one call");
-    return GAP_EINVAL;
-  }
-
-  DevBuf d_src, d_dst, d_keys, d_sorted, d_flag, d_pos, d_bad, d_tmp, d_maxdeg;
-  GAP_HIP(d_src.alloc(sizeof(int32_t) * (size_t)m));
-  GAP_HIP(d_dst.alloc(sizeof(int32_t) * (size_t)m));
-  GAP_HIP(d_keys.alloc(sizeof(uint64_t) * (size_t)len));
-  GAP_HIP(d_sorted.alloc(sizeof(uint64_t) * (size_t)len));
+  const int64_t len = mode == 0 ? 2 * m : m;
+  DevBuf d_keys, d_sorted, d_flag, d_pos, d_bad, d_tmp, d_maxdeg;
+  GAP_HIP(d_keys.alloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1)));
+  GAP_HIP(d_sorted.alloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1)));
   GAP_HIP(d_bad.alloc(sizeof(int)));
   GAP_HIP(d_maxdeg.alloc(sizeof(unsigned long long)));
-  if (m > 0) {
-    GAP_HIP(hipMemcpyAsync(d_src.p, src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
-                           stream));
-    GAP_HIP(hipMemcpyAsync(d_dst.p, dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
-                           stream));
-  }
   GAP_HIP(hipMemsetAsync(d_bad.p, 0, sizeof(int), stream));
   GAP_HIP(hipMemsetAsync(d_maxdeg.p, 0, sizeof(unsigned long long), stream));
   int64_t nnz = 0;
   if (m > 0) {
-    k_make_keys<<<grid_for(m), 256, 0, stream>>>(d_src.as<int32_t>(), d_dst.as<int32_t>(), m, n,
-                                                 bits, sentinel, d_keys.as<uint64_t>(),
-                                                 d_bad.as<int>());
+    k_make_keys<<<grid_for(m), 256, 0, stream>>>(d_src, d_dst, m, n, bits, sentinel, mode,
+                                                 d_keys.as<uint64_t>(), d_bad.as<int>());
     GAP_HIP(hipGetLastError());
     int h_bad = 0;
     GAP_HIP(hipMemcpyAsync(&h_bad, d_bad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -145,11 +138,6 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
       set_error("gap_build_csr: an edge endpoint is outside [0, n)");
       return GAP_EINVAL;
     }
-    // free the raw pairs early: the sort needs the room at large scales
-    (void)hipFree(d_src.p);
-    d_src.p = nullptr;
-    (void)hipFree(d_dst.p);
-    d_dst.p = nullptr;
     size_t tmp_bytes = 0;
     GAP_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, d_keys.as<uint64_t>(),
                                      d_sorted.as<uint64_t>(), (size_t)len, 0u,
@@ -160,8 +148,6 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
                                      (unsigned)(2 * bits), stream));
     (void)hipFree(d_tmp.p);
     d_tmp.p = nullptr;
-    // flags (uint32) and positions (int64) reuse the unsorted key buffer when
-    // it is large enough: len*8 bytes >= len*4 + len*8 is false, so allocate.
     GAP_HIP(d_flag.alloc(sizeof(uint32_t) * (size_t)len));
     GAP_HIP(d_pos.alloc(sizeof(int64_t) * (size_t)len));
     k_mark_unique<<<grid_for(len), 256, 0, stream>>>(d_sorted.as<uint64_t>(), len, sentinel,
@@ -184,24 +170,13 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
     GAP_HIP(hipStreamSynchronize(stream));
     nnz = last_pos + (int64_t)last_flag;
   }
-
-  gap_graph *g = new (std::nothrow) gap_graph();
-  if (!g) {
-    set_error("gap_build_csr: host allocation failed");
-    return GAP_ENOMEM;
-  }
-  g->device = dev;
-  g->n = n;
-  g->nnz = nnz;
-  g->row_ptr = nullptr;
-  g->col = nullptr;
-  g->max_degree = 0;
-  hipError_t e1 = hipMalloc(&g->row_ptr, sizeof(int64_t) * (size_t)(n + 1));
-  hipError_t e2 = hipMalloc(&g->col, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int64_t *row_ptr = nullptr;
+  int32_t *col = nullptr;
+  hipError_t e1 = hipMalloc(&row_ptr, sizeof(int64_t) * (size_t)(n + 1));
+  hipError_t e2 = hipMalloc(&col, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
   if (e1 != hipSuccess || e2 != hipSuccess) {
-    if (g->row_ptr) (void)hipFree(g->row_ptr);
-    if (g->col) (void)hipFree(g->col);
-    delete g;
+    if (row_ptr) (void)hipFree(row_ptr);
+    if (col) (void)hipFree(col);
     set_error("gap_build_csr: device allocation of the CSR failed");
     return GAP_ENOMEM;
   }
@@ -209,24 +184,77 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
     // distinct keys go to the (now free) unsorted key buffer
     k_scatter_cols<<<grid_for(len), 256, 0, stream>>>(d_sorted.as<uint64_t>(),
                                                       d_flag.as<uint32_t>(), d_pos.as<int64_t>(),
-                                                      len, mask, g->col, d_keys.as<uint64_t>());
+                                                      len, mask, col, d_keys.as<uint64_t>());
   }
-  k_row_ptr<<<grid_for(nnz + 1), 256, 0, stream>>>(d_keys.as<uint64_t>(), nnz, n, bits,
-                                                   g->row_ptr);
-  k_max_degree<<<grid_for(n), 256, 0, stream>>>(g->row_ptr, n,
-                                                d_maxdeg.as<unsigned long long>());
+  k_row_ptr<<<grid_for(nnz + 1), 256, 0, stream>>>(d_keys.as<uint64_t>(), nnz, n, bits, row_ptr);
+  k_max_degree<<<grid_for(n), 256, 0, stream>>>(row_ptr, n, d_maxdeg.as<unsigned long long>());
   hipError_t le = hipGetLastError();
   unsigned long long maxdeg = 0;
   hipError_t ce = hipMemcpyAsync(&maxdeg, d_maxdeg.p, sizeof(maxdeg), hipMemcpyDeviceToHost,
                                  stream);
   hipError_t se = hipStreamSynchronize(stream);
   if (le != hipSuccess || ce != hipSuccess || se != hipSuccess) {
-    (void)hipFree(g->row_ptr);
-    (void)hipFree(g->col);
-    delete g;
+    (void)hipFree(row_ptr);
+    (void)hipFree(col);
     return hip_fail(le != hipSuccess ? le : (ce != hipSuccess ? ce : se), "gap_build_csr kernels");
   }
-  g->max_degree = (int64_t)maxdeg;
+  *row_ptr_out = row_ptr;
+  *col_out = col;
+  *nnz_out = nnz;
+  *maxdeg_out = (int64_t)maxdeg;
+  return GAP_OK;
+}
+
+gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, bool directed,
+                     hipStream_t stream, gap_graph **out) {
+  int dev = 0;
+  GAP_HIP(hipGetDevice(&dev));
+  int bits = 1;
+  while (bits < 31 && (1ll << bits) < n) ++bits;
+  if ((directed ? m : 2 * m) >= (1ll << 32)) {
+    set_error("gap_build_csr: more than 2^32 directed entries in one call");
+    return GAP_EINVAL;
+  }
+  DevBuf d_src, d_dst;
+  GAP_HIP(d_src.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+  GAP_HIP(d_dst.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+  if (m > 0) {
+    GAP_HIP(hipMemcpyAsync(d_src.p, src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
+                           stream));
+    GAP_HIP(hipMemcpyAsync(d_dst.p, dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
+                           stream));
+  }
+  gap_graph *g = new (std::nothrow) gap_graph();
+  if (!g) {
+    set_error("gap_build_csr: host allocation failed");
+    return GAP_ENOMEM;
+  }
+  g->device = dev;
+  g->n = n;
+  g->directed = directed ? 1 : 0;
+  // undirected: one symmetric CSR serves both directions; directed: the
+  // out-lists (top-down) and the in-lists (bottom-up)
+  gap_status st = csr_pass(d_src.as<int32_t>(), d_dst.as<int32_t>(), n, m, bits, directed ? 1 : 0,
+                           stream, &g->row_ptr, &g->col, &g->nnz, &g->max_degree);
+  if (st != GAP_OK) {
+    delete g;
+    return st;
+  }
+  if (directed) {
+    int64_t maxdeg_in = 0;
+    st = csr_pass(d_src.as<int32_t>(), d_dst.as<int32_t>(), n, m, bits, 2, stream,
+                  &g->row_ptr_in, &g->col_in, &g->nnz_in, &maxdeg_in);
+    if (st != GAP_OK) {
+      (void)hipFree(g->row_ptr);
+      (void)hipFree(g->col);
+      delete g;
+      return st;
+    }
+  } else {
+    g->row_ptr_in = g->row_ptr;
+    g->col_in = g->col;
+    g->nnz_in = g->nnz;
+  }
   *out = g;
   return GAP_OK;
 }

@@ -21,10 +21,13 @@ constexpr int32_t kIsolated = INT32_MIN;
 constexpr int kGroups = 16;
 
 struct DevGraph {
-  const int64_t *row_ptr;  // int64[n+1]
-  const int32_t *col;      // int32[nnz], each row ascending
+  const int64_t *row_ptr;     // int64[n+1], out-lists (top-down)
+  const int32_t *col;         // int32[nnz], each row ascending
+  const int64_t *row_ptr_in;  // in-lists (bottom-up); the same arrays when undirected
+  const int32_t *col_in;
   int64_t n;
   int64_t nnz;
+  int32_t directed;
 };
 
 // Level totals reduced across the grid.

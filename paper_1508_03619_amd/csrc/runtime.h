@@ -14,10 +14,14 @@
 
 struct gap_graph {
   int device;
+  int directed;         // 1: out-lists and in-lists differ
   int64_t n;
-  int64_t nnz;
-  int64_t *row_ptr;  // device int64[n+1]
-  int32_t *col;      // device int32[nnz]
+  int64_t nnz;          // out-list entries
+  int64_t *row_ptr;     // device int64[n+1], out-lists
+  int32_t *col;         // device int32[nnz]
+  int64_t nnz_in;       // in-list entries (== nnz)
+  int64_t *row_ptr_in;  // device in-lists; the same arrays as row_ptr/col when undirected
+  int32_t *col_in;
   int64_t max_degree;
 };
 
@@ -130,7 +134,7 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
                          hipStream_t stream, const gap_params &p);
 // Implemented in build_csr.hip
-gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, bool directed,
                      hipStream_t stream, gap_graph **out);
 gap_status stream_copy(void *dst, const void *src, int64_t bytes, hipStream_t stream);
 

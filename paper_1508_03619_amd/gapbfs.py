@@ -58,7 +58,8 @@ class DeviceInfo(ctypes.Structure):
                 ("total_mem", ctypes.c_int64), ("arch", ctypes.c_char * 64)]
 
 
-EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_bfs", "gap_bfs_batch",
+EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_export",
+            "gap_graph_export_in", "gap_bfs", "gap_bfs_batch",
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
             "gap_device_query", "gap_stream_copy"]
 
@@ -87,6 +88,8 @@ def load():
         L.gap_build_csr.argtypes = [i64, i64, i32p, i32p, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
         L.gap_graph_info.argtypes = [vp, i64p, i64p]
         L.gap_graph_export.argtypes = [vp, i64p, i32p]
+        L.gap_graph_export_in.argtypes = [vp, i64p, i32p]
+        L.gap_graph_directed.argtypes = [vp]
         L.gap_bfs.argtypes = [vp, i32, vp, vp, vp]
         L.gap_bfs_ex.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(_Params),
                                  ctypes.POINTER(LevelStat), i32, i32p]
@@ -100,7 +103,8 @@ def load():
         L.gap_get_params.argtypes = [ctypes.POINTER(_Params)]
         L.gap_device_query.argtypes = [ctypes.POINTER(DeviceInfo)]
         L.gap_stream_copy.argtypes = [vp, vp, i64, vp]
-        for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_bfs", "gap_bfs_ex",
+        for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_graph_export_in",
+                     "gap_graph_directed", "gap_bfs", "gap_bfs_ex",
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
                      "gap_stream_copy"):
             getattr(L, name).restype = ctypes.c_int32
@@ -175,13 +179,17 @@ def _i32p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
 
 
+BUILD_DIRECTED = 1  # gap_build_csr flag
+
+
 class Graph:
     """A CSR graph resident in device memory (owns its gap_graph handle)."""
 
-    def __init__(self, handle: int, n: int, nnz: int):
+    def __init__(self, handle: int, n: int, nnz: int, directed: bool = False):
         self.handle = ctypes.c_void_p(handle)
         self.n = n
         self.nnz = nnz
+        self.directed = directed
 
     def free(self):
         if self.handle and self.handle.value:
@@ -194,35 +202,46 @@ class Graph:
         except Exception:
             pass
 
-    def export(self):
-        """(row_ptr int64[n+1], col int32[nnz]) copied to the host."""
+    def _export(self, fn, with_col=True):
         row_ptr = np.empty(self.n + 1, np.int64)
-        col = np.empty(max(self.nnz, 1), np.int32)
-        _check(load().gap_graph_export(self.handle, row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                       _i32p(col)))
-        return row_ptr, col[:self.nnz]
+        col = np.empty(max(self.nnz, 1), np.int32) if with_col else None
+        _check(fn(self.handle, row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                  _i32p(col) if with_col else None))
+        return row_ptr, (col[:self.nnz] if with_col else None)
+
+    def export(self):
+        """(row_ptr int64[n+1], col int32[nnz]) copied to the host: the
+        out-lists of a directed graph."""
+        return self._export(load().gap_graph_export)
+
+    def export_in(self):
+        """The in-lists (the transpose), as ``export``."""
+        return self._export(load().gap_graph_export_in)
 
     def degrees(self) -> np.ndarray:
         rp, _ = self.export_row_ptr()
         return np.diff(rp)
 
     def export_row_ptr(self):
-        row_ptr = np.empty(self.n + 1, np.int64)
-        _check(load().gap_graph_export(self.handle, row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                       None))
-        return row_ptr, None
+        return self._export(load().gap_graph_export, with_col=False)
 
 
-def build_csr(n: int, src: np.ndarray, dst: np.ndarray, stream=None) -> Graph:
+def build_csr(n: int, src: np.ndarray, dst: np.ndarray, stream=None, directed: bool = False) -> Graph:
+    """Build the device CSR from raw pairs (copied).  ``directed`` keeps
+    src[i] -> dst[i] as a one-way edge; otherwise every pair is undirected."""
     L = load()
     src = np.ascontiguousarray(src, dtype=np.int32)
     dst = np.ascontiguousarray(dst, dtype=np.int32)
     out = ctypes.c_void_p()
-    _check(L.gap_build_csr(int(n), int(src.shape[0]), _i32p(src), _i32p(dst), 0,
-                           _stream_handle(stream), ctypes.byref(out)))
+    _check(L.gap_build_csr(int(n), int(src.shape[0]), _i32p(src), _i32p(dst),
+                           BUILD_DIRECTED if directed else 0, _stream_handle(stream),
+                           ctypes.byref(out)))
     nn, nnz = ctypes.c_int64(), ctypes.c_int64()
     _check(L.gap_graph_info(out, ctypes.byref(nn), ctypes.byref(nnz)))
-    return Graph(out.value, nn.value, nnz.value)
+    dflag = L.gap_graph_directed(out)
+    if dflag < 0:
+        _check(dflag)
+    return Graph(out.value, nn.value, nnz.value, directed=bool(dflag))
 
 
 def graph_info(g: Graph):

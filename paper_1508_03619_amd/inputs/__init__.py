@@ -61,6 +61,8 @@ def _load():
         lib.gapgen_pick_sources.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p,
                                             ctypes.c_uint64, ctypes.c_int32, i32p]
         lib.gapgen_pick_sources.restype = ctypes.c_int32
+        lib.gapgen_pick_out_sources.argtypes = lib.gapgen_pick_sources.argtypes
+        lib.gapgen_pick_out_sources.restype = ctypes.c_int32
         lib.gapgen_set_threads.argtypes = [ctypes.c_int]
         lib.gapgen_set_threads.restype = None
         lib.gapgen_max_threads.argtypes = []
@@ -151,13 +153,14 @@ def shortcut_count(w: int, h: int, frac: float) -> int:
     return int(_load().gapgen_grid_num_shortcuts(int(w), int(h), float(frac)))
 
 
-def pick_sources(el: EdgeList, k: int = 64, seed: int = 1) -> np.ndarray:
-    """Up to k distinct uniform-random vertices with non-zero degree."""
+def pick_sources(el: EdgeList, k: int = 64, seed: int = 1, directed: bool = False) -> np.ndarray:
+    """Up to k distinct uniform-random vertices with non-zero degree (with
+    ``directed``, non-zero out-degree: pair e is the edge src[e] -> dst[e])."""
     out = np.empty(max(int(k), 1), dtype=np.int32)
-    got = _load().gapgen_pick_sources(int(el.n), int(el.m), _p(el.src), _p(el.dst),
-                                      int(seed) & (2**64 - 1), int(k), _p(out))
+    fn = _load().gapgen_pick_out_sources if directed else _load().gapgen_pick_sources
+    got = fn(int(el.n), int(el.m), _p(el.src), _p(el.dst), int(seed) & (2**64 - 1), int(k), _p(out))
     if got < 0:
-        raise ValueError("gapgen_pick_sources rejected its arguments")
+        raise ValueError("the source picker rejected its arguments")
     return out[:got].copy()
 
 
@@ -168,6 +171,10 @@ def workload(name: str) -> EdgeList:
         return rmat(16, 16, seed=16001)
     if name == "rmat22":
         return rmat(22, 16, seed=22001)
+    if name == "rmat16d":  # the pairs taken as directed edges (skewed, like a social graph)
+        return rmat(16, 16, seed=16003)
+    if name == "rmat22d":
+        return rmat(22, 16, seed=22003)
     if name == "urand22":
         e = urand_scale(22, 16, seed=22002)
         return e
@@ -179,4 +186,8 @@ def workload(name: str) -> EdgeList:
 
 
 SOURCE_SEEDS = {"rmat16": 1016001, "rmat22": 1022001, "urand22": 1022002,
-                "rmat24": 1024001, "grid4096": 1040960}
+                "rmat24": 1024001, "grid4096": 1040960, "rmat16d": 1016003, "rmat22d": 1022003}
+
+# Workloads whose pairs are directed edges (build with directed=True, pick
+# sources with directed=True).
+DIRECTED = {"rmat16d", "rmat22d"}

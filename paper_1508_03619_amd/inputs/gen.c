@@ -286,9 +286,9 @@ int64_t gapgen_grid(int w, int h, double p_delete, double shortcut_frac,
  * symmetrised and cleaned) and that were not picked before.  Writes up to k
  * sources, returns how many were found (fewer only if the graph has fewer
  * non-zero-degree vertices, or after 64*n + 1024 draws). */
-int32_t gapgen_pick_sources(int64_t n, int64_t m, const int32_t *src,
+static int32_t pick_sources(int64_t n, int64_t m, const int32_t *src,
                             const int32_t *dst, uint64_t seed, int32_t k,
-                            int32_t *out) {
+                            int32_t *out, int out_only) {
   if (n < 1 || m < 0 || k < 0 || !out || (m > 0 && (!src || !dst))) return -1;
   uint8_t *touch = (uint8_t *)calloc((size_t)n, 1);
   if (!touch) return -1;
@@ -296,7 +296,7 @@ int32_t gapgen_pick_sources(int64_t n, int64_t m, const int32_t *src,
     int32_t a = src[e], b = dst[e];
     if (a == b || a < 0 || b < 0 || a >= n || b >= n) continue;
     touch[a] = 1;
-    touch[b] = 1;
+    if (!out_only) touch[b] = 1;
   }
   const uint64_t key = stream_key(seed, TAG_SOURCES);
   int32_t got = 0;
@@ -311,4 +311,18 @@ int32_t gapgen_pick_sources(int64_t n, int64_t m, const int32_t *src,
   }
   free(touch);
   return got;
+}
+
+int32_t gapgen_pick_sources(int64_t n, int64_t m, const int32_t *src,
+                            const int32_t *dst, uint64_t seed, int32_t k,
+                            int32_t *out) {
+  return pick_sources(n, m, src, dst, seed, k, out, 0);
+}
+
+/* As gapgen_pick_sources for a directed graph (pair e is the edge
+ * src[e] -> dst[e]): only vertices with an out-edge qualify. */
+int32_t gapgen_pick_out_sources(int64_t n, int64_t m, const int32_t *src,
+                                const int32_t *dst, uint64_t seed, int32_t k,
+                                int32_t *out) {
+  return pick_sources(n, m, src, dst, seed, k, out, 1);
 }

@@ -51,6 +51,12 @@ def test_argument_errors_without_device(lib):
     assert lib.gap_build_csr(2 ** 31, 0, None, None, 0, None, ctypes.byref(out)) == gapbfs.GAP_EINVAL
     # edges without arrays
     assert lib.gap_build_csr(4, 3, None, None, 0, None, ctypes.byref(out)) == gapbfs.GAP_EINVAL
+    # unknown flag bits (only GAP_BUILD_DIRECTED is defined)
+    s = (ctypes.c_int32 * 1)(0)
+    assert lib.gap_build_csr(4, 1, s, s, 2, None, ctypes.byref(out)) == gapbfs.GAP_EINVAL
+    assert b"flag" in lib.gap_last_error()
+    assert lib.gap_graph_directed(None) == gapbfs.GAP_EINVAL
+    assert lib.gap_graph_export_in(None, None, None) == gapbfs.GAP_EINVAL
     # NULL graph / parent
     assert lib.gap_bfs(None, 0, None, None, None) == gapbfs.GAP_EINVAL
     assert b"NULL" in lib.gap_last_error()

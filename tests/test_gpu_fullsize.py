@@ -1,8 +1,9 @@
 """Parity at the measured sizes, in the launch configuration the benchmark
 times: R-MAT scale 22 and uniform-random 2^22 (single-source and the
 64-lane batch), the 4096^2 road-like grid (persistent kernel and captured
-level graphs), R-MAT scale 24 in batches of 64 and 256 lanes, and the mixed
-batch of 16 R-MAT graphs of scales 14-20.
+level graphs), R-MAT scale 24 in batches of 64 and 256 lanes, the mixed
+batch of 16 R-MAT graphs of scales 14-20, and R-MAT scale 22 taken as a
+directed graph.
 
 Sampled searches are checked in full against the oracle (depths bit-exact,
 parents valid, Section 2.1).  Every lane of a large batch is also checked
@@ -186,3 +187,30 @@ def test_fullsize_mixed_batch(gpu, per_graph):
             assert int((D[i] >= 0).sum()) == int(size[lab[s]]), f"mixed graph {gi} lane {i}: reach"
     for g in graphs:
         g.free()
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_rmat22_directed(gpu):
+    """R-MAT scale 22 with the pairs as directed edges: sampled sources in
+    full against the directed oracle, in the configuration the benchmark
+    times, and the forced bottom-up and captured-level schedules."""
+    from paper_1508_03619_amd import inputs, gapbfs as gb
+    name = "rmat22d"
+    say(f"{name}: generating")
+    el = inputs.workload(name)
+    srcs = [int(x) for x in inputs.pick_sources(el, 64, seed=inputs.SOURCE_SEEDS[name], directed=True)]
+    say(f"{name}: building the directed device CSR")
+    g = gb.build_csr(el.n, el.src, el.dst, directed=True)
+    say(f"{name}: oracle adjacency")
+    A = oracle.Adjacency(el.n, el.src, el.dst, directed=True)
+    for i in (0, 21, 63):
+        say(f"{name}: search {i} (source {srcs[i]}) vs oracle")
+        ref = A.bfs(srcs[i])[0]
+        p, d = run_single(g, srcs[i])
+        assert_valid(A, srcs[i], p, d, ref, what=name)
+        if i == 0:
+            for sch in (dict(direction=2), dict(mode=2)):
+                say(f"{name}: {sch}")
+                p, d = run_single(g, srcs[i], params=sch)
+                assert_valid(A, srcs[i], p, d, ref, what=f"{name} {sch}")
+    g.free()

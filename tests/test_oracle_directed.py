@@ -182,3 +182,20 @@ def directed_pins_ok(L) -> bool:
 
 def test_directed_pin_function_passes(oracle_lib):
     assert directed_pins_ok(oracle_lib)
+
+
+def test_directed_source_picker():
+    """Sources of a directed workload have an out-edge, are distinct, and the
+    picker is deterministic in its seed."""
+    from paper_1508_03619_amd import inputs
+    # 0 -> 1 only: vertex 1 has in-degree 1 but no out-edge
+    el = inputs.EdgeList(4, np.array([0, 2, 3], np.int32), np.array([1, 2, 3], np.int32), "tiny")
+    assert inputs.pick_sources(el, 8, seed=3, directed=True).tolist() == [0]
+    assert sorted(inputs.pick_sources(el, 8, seed=3).tolist()) == [0, 1]
+    el = inputs.workload("rmat16d")
+    a = inputs.pick_sources(el, 64, seed=inputs.SOURCE_SEEDS["rmat16d"], directed=True)
+    b = inputs.pick_sources(el, 64, seed=inputs.SOURCE_SEEDS["rmat16d"], directed=True)
+    assert len(a) == 64 and len(set(a.tolist())) == 64 and np.array_equal(a, b)
+    keep = el.src != el.dst
+    outdeg = np.bincount(el.src[keep], minlength=el.n)
+    assert (outdeg[a] > 0).all()
