@@ -12,8 +12,9 @@ undirected edges in the source's connected component.
 
 Also reported, outside the timed steps: a 64-lane batched search over the
 same sources (per-source throughput vs repeated single-source searches), the
-measured stream-copy bandwidth, the roofline of the dominant kernel and the
-CPU oracle timed on a bounded sample.
+same R-MAT pairs taken as a directed graph, the serving loop, the measured
+stream-copy bandwidth, the roofline of the dominant kernel and the CPU
+oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -40,7 +41,7 @@ def log(msg):
 PROFILE_COPY_BYTES = 1 << 30
 
 
-def algorithmic_bytes(recs, n) -> int:
+def algorithmic_bytes(recs, n, directed=False) -> int:
     """Bytes the search must move (per launch), from per-level records.
 
     init: row_ptr read 8(n+1), parent+depth written 8n
@@ -49,6 +50,8 @@ def algorithmic_bytes(recs, n) -> int:
     bottom-up level, U unvisited, S_U scanned entries, H found:
         16|U| row_ptr + 4 S_U col + 3 n/8 bitmaps + 8|H|
     switch to bottom-up: 4|F| + n/8; final pass: 8n
+    directed graphs add, per bottom-up level, 16|H| for the out-degrees of
+    the found vertices, and at the switch 16|U| for the in-degree test
     """
     total = 8 * (n + 1) + 8 * n + 8 * n
     prev_dir = 1
@@ -58,7 +61,11 @@ def algorithmic_bytes(recs, n) -> int:
         else:
             if prev_dir == 1:
                 total += 4 * r["frontier"] + n // 8
+                if directed:
+                    total += 16 * r["unvisited"]
             total += 16 * r["unvisited"] + 4 * r["scanned"] + 3 * n // 8 + 8 * r["claimed"]
+            if directed:
+                total += 16 * r["claimed"]
         prev_dir = r["direction"]
     return int(total)
 
@@ -188,6 +195,52 @@ def leg_rmat24(gb, torch, inputs, stream):
     return out
 
 
+def leg_directed(gb, torch, inputs, stream):
+    """R-MAT scale 22 with the pairs taken as directed edges (out-lists for
+    top-down, in-lists for bottom-up): 64 single-source searches from
+    sources with an out-edge.  m_s is the number of directed edges leaving
+    the reached vertices (every one of them is examined)."""
+    t0 = time.time()
+    name = "rmat22d"
+    el = inputs.workload(name)
+    g = gb.build_csr(el.n, el.src, el.dst, directed=True)
+    srcs = [int(x) for x in inputs.pick_sources(el, 64, seed=inputs.SOURCE_SEEDS[name], directed=True)]
+    del el
+    outdeg = np.diff(g.export_row_ptr()[0])
+    p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ms, alg, levels = [], [], []
+    for s in srcs:
+        recs = gb.bfs(g, s, p, d, stats=True)
+        dd = d.cpu().numpy()
+        ms.append(int(outdeg[dd >= 0].sum()))
+        alg.append(algorithmic_bytes(recs, g.n, directed=True))
+        levels.append(len(recs))
+    build_s = time.time() - t0
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in srcs]
+    best = None
+    for rep in range(3):  # warm-up, then the better of two timed passes
+        for i, s in enumerate(srcs):
+            pairs[i][0].record(stream)
+            gb.bfs(g, s, p, d, stream=stream)
+            pairs[i][1].record(stream)
+        torch.cuda.synchronize()
+        t = np.array([a.elapsed_time(b) for a, b in pairs])
+        if rep > 0 and (best is None or t.sum() < best.sum()):
+            best = t
+    ms = np.array(ms, np.int64)
+    out = {"n": int(g.n), "nnz_out": int(g.nnz), "build_and_stats_s": round(build_s, 1),
+           "gteps_aggregate": round(float(ms.sum() / (best.sum() * 1e-3) / 1e9), 3),
+           "gteps_median_trial": round(float(np.median(ms / (best * 1e-3) / 1e9)), 3),
+           "trial_ms_median": round(float(np.median(best)), 4),
+           "levels_mean": round(float(np.mean(levels)), 1),
+           "mean_m_s": float(ms.mean()),
+           "alg_gbs_median": round(float(np.median(np.array(alg) / (best * 1e-3) / 1e9)), 1)}
+    log(f"{name}: {out}")
+    g.free()
+    return out
+
+
 MIXED_SCALES = [14, 14, 15, 15, 16, 16, 17, 17, 18, 18, 19, 19, 20, 20, 20, 20]
 
 
@@ -287,9 +340,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", default="rmat22,urand22")
-    ap.add_argument("--legs", default="serving",
-                    help="comma list of extra legs reported in detail: serving, grid4096, rmat24, "
-                         "mixed, or all")
+    ap.add_argument("--legs", default="serving,directed",
+                    help="comma list of extra legs reported in detail: serving, directed, grid4096, "
+                         "rmat24, mixed, or all")
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--profile-leg", action="store_true",
                     help="for rocprofv3 counter runs: a copy of known size, then one search per "
@@ -462,10 +515,12 @@ def main():
 
     legs = set(args.legs.split(",")) if args.legs else set()
     if "all" in legs:
-        legs = {"serving", "grid4096", "rmat24", "mixed"}
+        legs = {"serving", "directed", "grid4096", "rmat24", "mixed"}
     for c in cases:
         c.parent = c.depth = None
     torch.cuda.empty_cache()
+    if "directed" in legs:
+        detail["rmat22_directed"] = leg_directed(gb, torch, inputs, stream)
     if "grid4096" in legs:
         detail["grid4096"] = leg_grid(gb, torch, inputs, stream)
     if "rmat24" in legs:
