@@ -1,4 +1,5 @@
-"""CPU oracle for breadth-first search -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for breadth-first search and betweenness centrality -- TEST
+INFRASTRUCTURE ONLY.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The GPU library never calls it,
@@ -16,6 +17,10 @@ Definitions followed (the paper, arXiv 1508.03619):
   * Verification (Section 3, BFS verifier): a trivial serial BFS gives the
     reference depths; results are checked by properties, not by equality of
     parents, because several parent arrays are correct.
+  * Betweenness centrality (Section 2.1): score[v] sums sigma_st(v)/sigma_st
+    over the given sources s and all targets t, normalised so the largest
+    score is one; Brandes' method without recorded successors (the paper's
+    verifier for this kernel is also a serial Brandes, Section 3).
 
 The C implementation is ``oracle.c``; ``build()`` compiles it with gcc.
 """
@@ -69,6 +74,9 @@ def _bind(path: str):
     lib.oracle_check.restype = ctypes.c_int
     lib.oracle_components.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i32p]
     lib.oracle_components.restype = ctypes.c_int
+    lib.oracle_bc.argtypes = [ctypes.c_int64, i64p, i32p, ctypes.c_int32, i32p, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_double)]
+    lib.oracle_bc.restype = ctypes.c_int
     return lib
 
 
@@ -139,6 +147,17 @@ class Adjacency:
                                       _i32(np.ascontiguousarray(depth_ref, dtype=np.int32)),
                                       _i32(parent), dptr, ctypes.byref(bad))
         return int(code), int(bad.value)
+
+    def bc(self, sources, normalise: bool = True) -> np.ndarray:
+        """Betweenness scores (float64[n]) from the given sources."""
+        srcs = np.ascontiguousarray(sources, dtype=np.int32)
+        out = np.empty(self.n, dtype=np.float64)
+        r = self._lib.oracle_bc(self.n, _i64(self.offsets), _i32(self.adj), int(srcs.shape[0]),
+                                _i32(srcs), 1 if normalise else 0,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if r != 0:
+            raise ValueError("oracle_bc: bad input")
+        return out
 
     def component_edges(self, depth: np.ndarray) -> int:
         """Undirected edges inside the reached set: half the degree sum."""

@@ -99,3 +99,24 @@ def test_mutant_is_caught(tmp_path, name):
     except Exception:
         caught = True  # a crash-free exception (e.g. bad input detected) also counts
     assert caught, f"mutant {name} passed every pin"
+
+
+# Mistakes in the betweenness accumulation, caught by the betweenness pins.
+BC_MUTANTS = {
+    "bc_no_plus_one": [("* (1.0 + delta[v]);", "* (delta[v]);")],
+    "bc_ratio_inverted": [("sigma[w] / sigma[v] *", "sigma[v] / sigma[w] *")],
+    "bc_counts_predecessors": [("if (depth[v] == depth[u] + 1) sigma[v] += sigma[u];",
+                                "if (depth[v] == depth[u] + 1) sigma[v] += 1.0;")],
+    "bc_same_level_successor": [("        if (depth[v] == depth[w] + 1)\n          delta[w]",
+                                 "        if (depth[v] >= depth[w])\n          delta[w]")],
+    "bc_source_scored": [("      if (w != s) score[w] += delta[w];", "      score[w] += delta[w];")],
+    "bc_normalise_by_sum": [("      if (score[v] > top) top = score[v];", "      top += score[v];")],
+    "bc_sources_not_reset": [("      sigma[v] = 0.0;\n      delta[v] = 0.0;", "      sigma[v] = 0.0;")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(BC_MUTANTS))
+def test_bc_mutant_is_caught(tmp_path, name):
+    from tests import test_oracle_bc as TB
+    L = _compile_mutant(tmp_path, BC_MUTANTS[name])
+    assert not TB.bc_pins_ok(L), f"mutant {name} passed every betweenness pin"
