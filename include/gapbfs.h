@@ -154,6 +154,38 @@ gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          int32_t *const *parents, int32_t *const *depths,
                          void *stream);
 
+/* gap_bc flag: return the raw sums (no division by the largest score). */
+#define GAP_BC_RAW 1u
+
+/*
+ * gap_bc -- approximate betweenness centrality from a set of sources
+ * (Section 2.1, "Betweenness Centrality": the benchmark uses 4 sources and
+ * scores normalised to one).
+ *   g            graph from gap_build_csr (undirected or directed)
+ *   sources      host int32[num_sources], each in [0, n); a repeated source
+ *                contributes twice
+ *   num_sources  >= 1
+ *   scores       device double[n], written: score[v] = sum over the sources
+ *                s != v and all targets t != s, v of sigma_st(v) / sigma_st
+ *                (sigma_st: number of shortest s-t paths, sigma_st(v): those
+ *                through v; unweighted, along edge directions), then divided
+ *                by the largest score unless flags has GAP_BC_RAW (all-zero
+ *                scores stay zero)
+ *   flags        0 or GAP_BC_RAW
+ *   stream       queue for the work
+ * fp64 throughout.  Sums are formed in an order that depends on scheduling,
+ * so results may differ from run to run in the last bits.  Per-call scratch
+ * (about 32 bytes per vertex plus 8 bytes per 512 adjacency entries) comes
+ * from the per-stream pool.  The call waits on the stream once per source
+ * (to size the per-depth arrays) and returns with the last source's work
+ * queued.
+ * Errors: GAP_EINVAL (NULL argument, no sources, a source out of range, an
+ * unknown flag), GAP_ENOMEM, GAP_EDEVICE, GAP_EINTERNAL.
+ */
+gap_status gap_bc(const gap_graph *g, const int32_t *sources,
+                  int32_t num_sources, double *scores, uint32_t flags,
+                  void *stream);
+
 /* Releases the graph (NULL-safe).  Waits for the device to finish any work
  * queued on it before freeing. */
 void gap_free(gap_graph *g);

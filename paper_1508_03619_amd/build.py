@@ -17,12 +17,12 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgapbfs.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "bfs.hip", "msbfs.hip", "build_csr.hip"]
+SOURCES = ["api.hip", "bfs.hip", "msbfs.hip", "build_csr.hip", "bc.hip"]
 ARCH = os.environ.get("GAP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-    # packed-FP32 instructions stay off (no float math on this path anyway)
+    # packed-FP32 instructions stay off (the only float math here is fp64)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{INCLUDE}", f"-I{CSRC}",

@@ -344,6 +344,27 @@ gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes) 
   return GAP_OK;
 }
 
+gap_status workspace_reserve_bc(Workspace *ws, size_t vertex_bytes, size_t level_bytes) {
+  if (ws->bc_bytes < vertex_bytes) {
+    GAP_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->bc_buf) (void)hipFree(ws->bc_buf);
+    ws->bc_buf = nullptr;
+    ws->bc_bytes = 0;
+    GAP_HIP(hipMalloc(&ws->bc_buf, vertex_bytes));
+    ws->bc_bytes = vertex_bytes;
+  }
+  if (ws->bc_lv_bytes < level_bytes) {
+    GAP_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->bc_lv) (void)hipFree(ws->bc_lv);
+    ws->bc_lv = nullptr;
+    ws->bc_lv_bytes = 0;
+    GAP_HIP(hipMalloc(&ws->bc_lv, level_bytes));
+    ws->bc_lv_bytes = level_bytes;
+  }
+  if (!ws->bc_host) GAP_HIP(hipHostMalloc(&ws->bc_host, 256));
+  return GAP_OK;
+}
+
 }  // namespace gap
 
 using namespace gap;
@@ -565,6 +586,31 @@ void gap_free(gap_graph *g) {
   if (g->row_ptr) (void)hipFree(g->row_ptr);
   if (g->col) (void)hipFree(g->col);
   delete g;
+}
+
+gap_status gap_bc(const gap_graph *g, const int32_t *sources, int32_t num_sources, double *scores,
+                  uint32_t flags, void *stream) {
+  clear_error();
+  if (!g || !sources || !scores) {
+    set_error("gap_bc: NULL %s", !g ? "graph" : (!sources ? "sources" : "scores"));
+    return GAP_EINVAL;
+  }
+  if (num_sources < 1) {
+    set_error("gap_bc: num_sources = %d, need at least one", num_sources);
+    return GAP_EINVAL;
+  }
+  if ((flags & ~GAP_BC_RAW) != 0) {
+    set_error("gap_bc: unknown flag bits 0x%x", flags & ~GAP_BC_RAW);
+    return GAP_EINVAL;
+  }
+  for (int32_t i = 0; i < num_sources; ++i) {
+    if (sources[i] < 0 || (int64_t)sources[i] >= g->n) {
+      set_error("gap_bc: sources[%d] = %d outside [0, %lld)", i, sources[i], (long long)g->n);
+      return GAP_EINVAL;
+    }
+  }
+  GAP_HIP(hipSetDevice(g->device));
+  return run_bc(g, sources, num_sources, scores, (flags & GAP_BC_RAW) == 0, (hipStream_t)stream);
 }
 
 gap_status gap_stream_copy(void *dst, const void *src, int64_t bytes, void *stream) {

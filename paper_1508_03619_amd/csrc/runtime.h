@@ -86,12 +86,19 @@ struct Workspace {
   void *ms_buf = nullptr;
   size_t ms_host_bytes = 0;
   void *ms_host = nullptr;  // pinned staging for per-lane metadata
+  // betweenness centrality: per-vertex state, per-depth arrays, readback
+  size_t bc_bytes = 0;
+  void *bc_buf = nullptr;
+  size_t bc_lv_bytes = 0;
+  void *bc_lv = nullptr;
+  void *bc_host = nullptr;  // pinned, 256 bytes
 };
 
 Workspace *workspace_for(int dev, hipStream_t stream);
 gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const gap_params &p);
 gap_status workspace_reserve_recs(Workspace *ws, int32_t nrec);
 gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes);
+gap_status workspace_reserve_bc(Workspace *ws, size_t vertex_bytes, size_t level_bytes);
 
 // Persistent kernels need every workgroup resident at once.  Two of them
 // started on different streams could each get part of the machine and wait
@@ -133,6 +140,9 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          const int32_t *graph_of_source, const int32_t *sources,
                          int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
                          hipStream_t stream, const gap_params &p);
+// Implemented in bc.hip
+gap_status run_bc(const gap_graph *g, const int32_t *sources, int32_t num_sources, double *score,
+                  bool normalise, hipStream_t stream);
 // Implemented in build_csr.hip
 gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, bool directed,
                      hipStream_t stream, gap_graph **out);

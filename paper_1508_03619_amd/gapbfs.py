@@ -61,7 +61,7 @@ class DeviceInfo(ctypes.Structure):
 EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_export",
             "gap_graph_export_in", "gap_bfs", "gap_bfs_batch",
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
-            "gap_device_query", "gap_stream_copy"]
+            "gap_device_query", "gap_stream_copy", "gap_bc"]
 
 
 def library_path() -> str:
@@ -103,10 +103,11 @@ def load():
         L.gap_get_params.argtypes = [ctypes.POINTER(_Params)]
         L.gap_device_query.argtypes = [ctypes.POINTER(DeviceInfo)]
         L.gap_stream_copy.argtypes = [vp, vp, i64, vp]
+        L.gap_bc.argtypes = [vp, i32p, i32, vp, ctypes.c_uint32, vp]
         for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_graph_export_in",
                      "gap_graph_directed", "gap_bfs", "gap_bfs_ex",
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
-                     "gap_stream_copy"):
+                     "gap_stream_copy", "gap_bc"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
         _apply_tuned(L)
@@ -333,6 +334,24 @@ def bfs_batch(graphs: Sequence[Graph], graph_of_source: Sequence[int], sources: 
     if depths is not None:
         da = (ctypes.c_void_p * ns)(*[_ptr(t) for t in depths])
     _check(L.gap_bfs_batch(gh, ng, _i32p(gos), _i32p(src), ns, pa, da, _stream_handle(stream)))
+
+
+BC_RAW = 1  # gap_bc flag
+
+
+def bc(g: Graph, sources: Sequence[int], scores, normalise: bool = True, stream=None):
+    """Betweenness centrality from ``sources`` into ``scores`` (a contiguous
+    float64 device tensor of at least n entries), divided by the largest
+    score unless ``normalise`` is False."""
+    import torch
+    L = load()
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    if scores.dtype != torch.float64 or not scores.is_cuda or not scores.is_contiguous():
+        raise ValueError("scores must be a contiguous float64 device tensor")
+    if scores.numel() < g.n:
+        raise ValueError("scores shorter than n")
+    _check(L.gap_bc(g.handle, _i32p(src), int(src.shape[0]), scores.data_ptr(),
+                    0 if normalise else BC_RAW, _stream_handle(stream)))
 
 
 def device_query() -> dict:

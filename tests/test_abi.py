@@ -61,6 +61,8 @@ def test_argument_errors_without_device(lib):
     assert lib.gap_bfs(None, 0, None, None, None) == gapbfs.GAP_EINVAL
     assert b"NULL" in lib.gap_last_error()
     assert lib.gap_bfs_batch(None, 1, None, None, 1, None, None, None) == gapbfs.GAP_EINVAL
+    assert lib.gap_bc(None, None, 4, None, 0, None) == gapbfs.GAP_EINVAL
+    assert b"NULL" in lib.gap_last_error()
     lib.gap_free(None)  # NULL-safe
 
 
