@@ -12,7 +12,8 @@ undirected edges in the source's connected component.
 
 Also reported, outside the timed steps: a 64-lane batched search over the
 same sources (per-source throughput vs repeated single-source searches), the
-same R-MAT pairs taken as a directed graph, the serving loop, the measured
+same R-MAT pairs taken as a directed graph, betweenness centrality from 4
+sources, the serving loop, the measured
 stream-copy bandwidth, the roofline of the dominant kernel and the CPU
 oracle timed on a bounded sample.
 
@@ -241,6 +242,89 @@ def leg_directed(gb, torch, inputs, stream):
     return out
 
 
+def bc_bytes(A_rp, A_col, rows, depth, directed_in=None):
+    """Algorithmic bytes of the betweenness passes for one source (on top of
+    the search): grouping, path counts over in-lists, dependencies over
+    out-lists, accumulation.  Per reached vertex at depth >= 1 the forward
+    pass reads its list offsets (16), its order slot (4), col and depth of
+    every in-list entry (8 each) and sigma of every predecessor (8), and
+    stores sigma (8); per reached vertex below the deepest level the
+    backward pass reads offsets, order slot, col and depth of every out-list
+    entry and the 16-byte (sigma, S) pair of every successor, and stores S.
+    Grouping reads depth and list offsets twice and writes the order; the
+    accumulation reads the order, the pair and updates the score."""
+    n = len(depth)
+    reached = depth >= 0
+    R = int(reached.sum())
+    D = int(depth.max())
+    deg = np.diff(A_rp)
+    du, dv = depth[rows], depth[A_col]
+    succ = (du >= 0) & (dv == du + 1)           # out-list entries u -> v one level down
+    n_succ = np.bincount(rows[succ], minlength=n)
+    # every successor edge is a predecessor edge seen from the other end
+    fwd_v = reached & (depth >= 1)
+    bwd_v = reached & (depth < D)
+    deg_in = np.diff(directed_in) if directed_in is not None else deg
+    total = 20 * n + 2 * (4 * n + 16 * n) + 4 * R
+    total += int(fwd_v.sum()) * 28 + 8 * int(deg_in[fwd_v].sum()) + 8 * int(succ.sum())
+    total += int(bwd_v.sum()) * 28 + 8 * int(deg[bwd_v].sum()) + 16 * int(n_succ.sum())
+    total += 36 * R
+    return int(total)
+
+
+def leg_bc(gb, torch, inputs, stream):
+    """Betweenness centrality (Section 2.1: scores from 4 sources, normalised
+    to one) on R-MAT 22 and uniform 2^22: 8 trials of 4 sources each."""
+    out = {}
+    for name in ("rmat22", "urand22"):
+        el = inputs.workload(name)
+        g = gb.build_csr(el.n, el.src, el.dst)
+        del el
+        rp, col = g.export()
+        rows = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(rp))
+        srcs = [int(x) for x in inputs.pick_sources(inputs.workload(name), 32,
+                                                    seed=inputs.SOURCE_SEEDS[name] + 5)]
+        trials = [srcs[4 * i:4 * i + 4] for i in range(8)]
+        score = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        dd = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        ms = []
+        alg0 = 0
+        for i, tr in enumerate(trials):  # m_s per trial; bytes of the first trial (untimed)
+            m = 0
+            for s in tr:
+                recs = gb.bfs(g, s, p, dd, stats=True)
+                d = dd.cpu().numpy()
+                if i == 0:
+                    alg0 += algorithmic_bytes(recs, g.n) + bc_bytes(rp, col, rows, d)
+                m += int(np.diff(rp)[d >= 0].sum()) // 2
+            ms.append(m)
+        del col, rows
+        gb.bc(g, trials[0], score)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for tr in trials:
+            t0 = time.perf_counter()
+            e0.record(stream)
+            gb.bc(g, tr, score, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            times.append((e0.elapsed_time(e1), (time.perf_counter() - t0) * 1e3))
+        t = np.array([x[0] for x in times])
+        out[name] = {"trial_ms_median": round(float(np.median(t)), 3),
+                     "trial_ms_min": round(float(t.min()), 3),
+                     "wall_ms_median": round(float(np.median([x[1] for x in times])), 3),
+                     "gteps_median": round(float(np.median(np.array(ms) / (t * 1e-3) / 1e9)), 2),
+                     "alg_bytes_first_trial": int(alg0),
+                     "alg_gbs_first_trial": round(float(alg0 / (t[0] * 1e-3) / 1e9), 1)}
+        log(f"bc {name}: {out[name]}")
+        del score, p, dd
+        g.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 MIXED_SCALES = [14, 14, 15, 15, 16, 16, 17, 17, 18, 18, 19, 19, 20, 20, 20, 20]
 
 
@@ -340,9 +424,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", default="rmat22,urand22")
-    ap.add_argument("--legs", default="serving,directed",
-                    help="comma list of extra legs reported in detail: serving, directed, grid4096, "
-                         "rmat24, mixed, or all")
+    ap.add_argument("--legs", default="serving,directed,bc",
+                    help="comma list of extra legs reported in detail: serving, directed, bc, "
+                         "grid4096, rmat24, mixed, or all")
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--profile-leg", action="store_true",
                     help="for rocprofv3 counter runs: a copy of known size, then one search per "
@@ -515,12 +599,14 @@ def main():
 
     legs = set(args.legs.split(",")) if args.legs else set()
     if "all" in legs:
-        legs = {"serving", "directed", "grid4096", "rmat24", "mixed"}
+        legs = {"serving", "directed", "bc", "grid4096", "rmat24", "mixed"}
     for c in cases:
         c.parent = c.depth = None
     torch.cuda.empty_cache()
     if "directed" in legs:
         detail["rmat22_directed"] = leg_directed(gb, torch, inputs, stream)
+    if "bc" in legs:
+        detail["bc"] = leg_bc(gb, torch, inputs, stream)
     if "grid4096" in legs:
         detail["grid4096"] = leg_grid(gb, torch, inputs, stream)
     if "rmat24" in legs:

@@ -362,6 +362,7 @@ gap_status workspace_reserve_bc(Workspace *ws, size_t vertex_bytes, size_t level
     ws->bc_lv_bytes = level_bytes;
   }
   if (!ws->bc_host) GAP_HIP(hipHostMalloc(&ws->bc_host, 256));
+  if (!ws->bc_event) GAP_HIP(hipEventCreateWithFlags(&ws->bc_event, hipEventDisableTiming));
   return GAP_OK;
 }
 

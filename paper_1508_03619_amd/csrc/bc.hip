@@ -4,24 +4,38 @@
 // For each source s:
 //   1. a direction-optimizing search (the library's single-source kernel)
 //      gives depth[];
-//   2. the reached vertices are grouped by depth (counting sort: LDS bins per
-//      tile, one global reservation per bin and tile), and every vertex whose
-//      list is longer than kLight entries gets chunk items of kChunk entries;
-//   3. path counts, level by level away from s, pulled over in-lists:
+//   2. the reached vertices are grouped by (depth, length class of the
+//      list) with a counting sort (LDS bins per tile, one global reservation
+//      per bin and tile); a class-c list (at most 4 << c entries) is read by
+//      1 << c lanes in one round, and every list longer than kLong entries
+//      gets chunk items of kChunk entries instead (a directed graph has one
+//      grouping by in-list and one by out-list length);
+//   3. path counts, level by level away from s:
 //        sigma[v] = sum of sigma[u] over in-neighbours u one level up;
-//   4. dependencies, level by level towards s, pulled over out-lists.  With
+//   4. dependencies, level by level towards s.  With
 //        S[u] = sum over successors v (out-neighbours one level down) of
 //               (1 + delta[v]) / sigma[v] = 1 / sigma[v] + S[v],
 //      Brandes' dependency is delta[u] = sigma[u] * S[u], so a level reads
 //      only (sigma, S) of the level below and no per-vertex finishing step is
-//      needed between levels; chunk items add partial sums atomically;
+//      needed between levels;
 //   5. score[v] += sigma[v] * S[v] for every reached v != s.
+// Each level of steps 3 and 4 either pulls (every vertex of the level sums
+// over its own list: in-lists for sigma, out-lists for S) or pushes (every
+// vertex of the neighbouring level adds its value atomically to the
+// neighbours that lie in the level: out-lists for sigma, in-lists for S),
+// whichever reads fewer adjacency entries -- the direction choice of the
+// paper's BFS applied to the two passes of Brandes' method (pushes are
+// charged twice for their atomics).
 // Finally the scores are divided by the largest one (normalised to one),
 // unless the caller asks for raw sums.
 //
-// Successors are found by their depth, not recorded: the paper keeps a
-// successor bitmap to save memory over successor lists; this path keeps no
-// per-edge state at all.  fp64 throughout.
+// Level membership is probed in bitmaps of n bits, which stay in L2 where
+// the depth array would not.  Four bitmaps rotate (level d uses d mod 4):
+// while a level kernel reads the bitmap of its own or the neighbouring
+// level, it also marks the next level's vertices in a third (zeroing their
+// path state) and clears the fourth for the level after.  Successors are found this way, not recorded: the paper
+// keeps a successor bitmap to save memory over successor lists; this path
+// keeps no per-edge state.  fp64 throughout.
 
 #include <rocprim/device/device_scan.hpp>
 
@@ -32,10 +46,13 @@ namespace {
 
 constexpr int kBcBlock = 256;
 constexpr int kTile = 8192;     // vertices per workgroup in the grouping kernels
-constexpr int kLdsBins = 1024;  // depths counted in LDS; deeper ones use global atomics
-constexpr int kLight = 32;      // lists up to this long: one lane per vertex
-constexpr int kChunk = 512;     // entries per chunk item of a longer list
+constexpr int kLdsBins = 1024;  // keys counted in LDS; larger keys use global atomics
+constexpr int kGroupClasses = 6;  // lists of <= 4 << c entries: 1 << c lanes per vertex
+constexpr int kClasses = kGroupClasses + 1;  // the last class: chunk items
+constexpr int kLong = 4 << (kGroupClasses - 1);  // 128: longer lists become chunk items
+constexpr int kChunk = 512;     // entries per chunk item
 constexpr int kPerLane = kChunk / kWave;
+constexpr unsigned long long kPushWeight = 2;  // an atomic update costs about two probes
 
 // Per-vertex state read together by the level below: one 16-byte load.
 struct __align__(16) PathState {
@@ -43,192 +60,279 @@ struct __align__(16) PathState {
   double s;      // S = delta / sigma
 };
 
-__device__ inline double wave_sum_f64(double x) {
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
-}
-
 __device__ inline uint32_t chunks_of(int64_t deg) {
-  return deg > kLight ? (uint32_t)((deg + kChunk - 1) / kChunk) : 0u;
+  return deg > kLong ? (uint32_t)((deg + kChunk - 1) / kChunk) : 0u;
 }
 
-// ps <- (s ? 1 : 0, 0); *dmax <- max depth.
-__global__ __launch_bounds__(kBcBlock) void k_bc_init(int64_t n, const int32_t *__restrict__ depth,
-                                                      int32_t src, PathState *__restrict__ ps,
-                                                      int32_t *dmax) {
-  int32_t m = 0;
-  for (int64_t v = blockIdx.x * (int64_t)kBcBlock + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kBcBlock) {
-    ps[v] = PathState{v == src ? 1.0 : 0.0, 0.0};
-    m = max(m, depth[v]);
+// Class c < kGroupClasses holds lists of at most 4 << c entries (one round
+// of 4 loads per lane with 1 << c lanes per vertex).
+__device__ inline int length_class(int64_t deg) {
+  int c = 0;
+  while (c < kGroupClasses && deg > (4 << c)) ++c;
+  return c;
+}
+
+__device__ inline bool in_bitmap(const uint64_t *bm, int32_t u) {
+  return (bm[u >> 6] >> (u & 63)) & 1ull;
+}
+
+__device__ inline void mark(uint64_t *bm, int32_t v) {
+  atomicOr((unsigned long long *)&bm[v >> 6], 1ull << (v & 63));
+}
+
+// Workgroup maximum, then one atomic per workgroup.
+template <class T>
+__device__ inline void block_max_to(T m, T *out) {
+  __shared__ T part[kBcBlock / kWave];
+  for (int o = 32; o >= 1; o >>= 1) m = max(m, (T)__shfl_xor(m, o, kWave));
+  if (lane_id() == 0) part[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBcBlock / kWave; ++w) m = max(m, part[w]);
+    if (m > (T)0) atomicMax(out, m);
   }
-  for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-  if (lane_id() == 0 && m > 0) atomicMax(dmax, m);
 }
 
+// *dmax <- max depth; the four level bitmaps <- empty.
+__global__ __launch_bounds__(kBcBlock) void k_bc_start(int64_t n, const int32_t *__restrict__ depth,
+                                                       uint64_t *__restrict__ bms, int32_t *dmax) {
+  int32_t m = 0;
+  const int64_t stride = (int64_t)gridDim.x * kBcBlock;
+  const int64_t tid = blockIdx.x * (int64_t)kBcBlock + threadIdx.x;
+  for (int64_t v = tid; v < n; v += stride) m = max(m, depth[v]);
+  const int64_t words = 4 * ((n + 63) / 64);
+  for (int64_t w = tid; w < words; w += stride) bms[w] = 0ull;
+  block_max_to(m, dmax);
+}
+
+// One grouping of the reached vertices for one set of lists.
 struct GroupArgs {
   int64_t n;
+  int32_t max_depth;  // bins exist for depths up to here; deeper vertices are left out
   const int32_t *depth;
-  const int64_t *rp_in, *rp_out;  // rp_out == nullptr: undirected, one item set
-  uint32_t *cnt, *icnt_in, *icnt_out;  // per depth: vertices, chunk items
+  const int64_t *rp;  // the lists whose lengths set the class and the chunk items
+  uint32_t *cnt;      // per key = depth * kClasses + class: vertices
+  uint32_t *icnt;     // per depth: chunk items
+  unsigned long long *esum;  // per depth: list entries (count pass only)
   int32_t *order;
-  int2 *items_in, *items_out;
+  int2 *items;
 };
 
-// Per depth: number of reached vertices and of chunk items.
+__device__ inline void vertex_key(const GroupArgs &a, int64_t v, int32_t d, int64_t *key,
+                                  uint32_t *nch, int64_t *deg) {
+  *deg = a.rp[v + 1] - a.rp[v];
+  *key = (int64_t)d * kClasses + length_class(*deg);
+  *nch = chunks_of(*deg);
+}
+
+// Counts per key, and chunk items and list entries per depth.
 __global__ __launch_bounds__(kBcBlock) void k_bc_count(GroupArgs a) {
-  __shared__ uint32_t c[kLdsBins], ci[kLdsBins], co[kLdsBins];
-  for (int b = threadIdx.x; b < kLdsBins; b += kBcBlock) c[b] = ci[b] = co[b] = 0;
+  __shared__ uint32_t c[kLdsBins], ci[kLdsBins];
+  __shared__ unsigned long long ce[kLdsBins];
+  for (int b = threadIdx.x; b < kLdsBins; b += kBcBlock) {
+    c[b] = ci[b] = 0;
+    ce[b] = 0;
+  }
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kTile;
   const int64_t end = min(base + kTile, a.n);
   for (int64_t v = base + threadIdx.x; v < end; v += kBcBlock) {
     const int32_t d = a.depth[v];
-    if (d < 0) continue;
-    const uint32_t ni = chunks_of(a.rp_in[v + 1] - a.rp_in[v]);
-    const uint32_t no = a.rp_out ? chunks_of(a.rp_out[v + 1] - a.rp_out[v]) : 0u;
+    if (d < 0 || d > a.max_depth) continue;
+    int64_t key, deg;
+    uint32_t nch;
+    vertex_key(a, v, d, &key, &nch, &deg);
+    if (key < kLdsBins)
+      atomicAdd(&c[key], 1u);
+    else
+      atomicAdd(&a.cnt[key], 1u);
     if (d < kLdsBins) {
-      atomicAdd(&c[d], 1u);
-      if (ni) atomicAdd(&ci[d], ni);
-      if (no) atomicAdd(&co[d], no);
+      if (nch) atomicAdd(&ci[d], nch);
+      if (deg) atomicAdd(&ce[d], (unsigned long long)deg);
     } else {
-      atomicAdd(&a.cnt[d], 1u);
-      if (ni) atomicAdd(&a.icnt_in[d], ni);
-      if (no) atomicAdd(&a.icnt_out[d], no);
+      if (nch) atomicAdd(&a.icnt[d], nch);
+      if (deg) atomicAdd(&a.esum[d], (unsigned long long)deg);
     }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kLdsBins; b += kBcBlock) {
     if (c[b]) atomicAdd(&a.cnt[b], c[b]);
-    if (ci[b]) atomicAdd(&a.icnt_in[b], ci[b]);
-    if (co[b]) atomicAdd(&a.icnt_out[b], co[b]);
+    if (ci[b]) atomicAdd(&a.icnt[b], ci[b]);
+    if (ce[b]) atomicAdd(&a.esum[b], ce[b]);
   }
 }
 
-// Places vertices in order[] and chunk items in items_*[] at the positions
-// reserved from the cursors (cnt / icnt_* hold the level starts on entry).
+// Places vertices in order[] and chunk items in items[] at positions
+// reserved from the cursors (cnt / icnt hold the bin starts on entry).
 __global__ __launch_bounds__(kBcBlock) void k_bc_scatter(GroupArgs a) {
-  __shared__ uint32_t c[kLdsBins], ci[kLdsBins], co[kLdsBins];
-  __shared__ uint32_t b0[kLdsBins], bi[kLdsBins], bo[kLdsBins];
-  for (int b = threadIdx.x; b < kLdsBins; b += kBcBlock) c[b] = ci[b] = co[b] = 0;
+  __shared__ uint32_t c[kLdsBins], ci[kLdsBins], b0[kLdsBins], bi[kLdsBins];
+  for (int b = threadIdx.x; b < kLdsBins; b += kBcBlock) c[b] = ci[b] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kTile;
   const int64_t end = min(base + kTile, a.n);
   for (int64_t v = base + threadIdx.x; v < end; v += kBcBlock) {
     const int32_t d = a.depth[v];
-    if (d < 0 || d >= kLdsBins) continue;
-    const uint32_t ni = chunks_of(a.rp_in[v + 1] - a.rp_in[v]);
-    const uint32_t no = a.rp_out ? chunks_of(a.rp_out[v + 1] - a.rp_out[v]) : 0u;
-    atomicAdd(&c[d], 1u);
-    if (ni) atomicAdd(&ci[d], ni);
-    if (no) atomicAdd(&co[d], no);
+    if (d < 0 || d > a.max_depth) continue;
+    int64_t key, deg;
+    uint32_t nch;
+    vertex_key(a, v, d, &key, &nch, &deg);
+    if (key < kLdsBins) atomicAdd(&c[key], 1u);
+    if (nch && d < kLdsBins) atomicAdd(&ci[d], nch);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kLdsBins; b += kBcBlock) {
     b0[b] = c[b] ? atomicAdd(&a.cnt[b], c[b]) : 0u;
-    bi[b] = ci[b] ? atomicAdd(&a.icnt_in[b], ci[b]) : 0u;
-    bo[b] = co[b] ? atomicAdd(&a.icnt_out[b], co[b]) : 0u;
-    c[b] = ci[b] = co[b] = 0;  // reused as in-tile cursors
+    bi[b] = ci[b] ? atomicAdd(&a.icnt[b], ci[b]) : 0u;
+    c[b] = ci[b] = 0;  // reused as in-tile cursors
   }
   __syncthreads();
   for (int64_t v = base + threadIdx.x; v < end; v += kBcBlock) {
     const int32_t d = a.depth[v];
-    if (d < 0) continue;
-    const uint32_t ni = chunks_of(a.rp_in[v + 1] - a.rp_in[v]);
-    const uint32_t no = a.rp_out ? chunks_of(a.rp_out[v + 1] - a.rp_out[v]) : 0u;
-    uint32_t pos, ipos = 0, opos = 0;
-    if (d < kLdsBins) {
-      pos = b0[d] + atomicAdd(&c[d], 1u);
-      if (ni) ipos = bi[d] + atomicAdd(&ci[d], ni);
-      if (no) opos = bo[d] + atomicAdd(&co[d], no);
-    } else {
-      pos = atomicAdd(&a.cnt[d], 1u);
-      if (ni) ipos = atomicAdd(&a.icnt_in[d], ni);
-      if (no) opos = atomicAdd(&a.icnt_out[d], no);
-    }
+    if (d < 0 || d > a.max_depth) continue;
+    int64_t key, deg;
+    uint32_t nch;
+    vertex_key(a, v, d, &key, &nch, &deg);
+    const uint32_t pos = key < kLdsBins ? b0[key] + atomicAdd(&c[key], 1u) : atomicAdd(&a.cnt[key], 1u);
     a.order[pos] = (int32_t)v;
-    for (uint32_t k = 0; k < ni; ++k) a.items_in[ipos + k] = make_int2((int)v, (int)k);
-    for (uint32_t k = 0; k < no; ++k) a.items_out[opos + k] = make_int2((int)v, (int)k);
+    if (nch) {
+      const uint32_t ipos = d < kLdsBins ? bi[d] + atomicAdd(&ci[d], nch) : atomicAdd(&a.icnt[d], nch);
+      for (uint32_t k = 0; k < nch; ++k) a.items[ipos + k] = make_int2((int)v, (int)k);
+    }
   }
 }
 
-struct LevelArgs {
+// A grouping as the level kernels read it.
+struct GroupView {
   const int32_t *order;
-  const uint32_t *off;   // level starts in order[], [D + 2]
+  const uint32_t *off;   // key starts in order[], [(D + 1) * kClasses + 1]
   const int2 *items;
-  const uint32_t *ioff;  // level starts in items[], [D + 2]
-  const int64_t *rp;     // in-lists (forward) or out-lists (backward)
-  const int32_t *col;
-  const int32_t *depth;
+  const uint32_t *ioff;  // depth starts in items[], [D + 2]
+  const unsigned long long *esum;  // list entries per depth
+};
+
+struct LevelArgs {
+  GroupView gin, gout;  // grouped by in-list / out-list length (the same when undirected)
+  const int64_t *rp_in, *rp_out;
+  const int32_t *col_in, *col_out;
+  uint64_t *bms;        // four bitmaps of nwords words
+  int64_t nwords;
+  int32_t dmax;
   PathState *ps;
 };
 
-// One level.  FORWARD: sigma of level d from level d - 1 over in-lists.
-// Backward: S of level d from level d + 1 over out-lists.  Wave tasks: first
-// the level's vertices 64 at a time (one lane each, lists up to kLight), then
-// one chunk item each.
+// Level d of the forward (sigma) or backward (S) pass.  Wave tasks, in
+// order: for each length class c, 64 >> c vertices with 1 << c lanes each
+// (a list read in one round of 4 loads per lane); then one chunk item each.
+// Pull: the tasks cover level d and sum over its lists.  Push: they cover
+// the neighbouring level and add along its lists into level d.  Before that
+// every thread helps mark the next level and clear the bitmap after it.
 template <bool FORWARD>
 __global__ __launch_bounds__(kBcBlock) void k_bc_level(LevelArgs a, int32_t d) {
-  const uint32_t lo = a.off[d], nv = a.off[d + 1] - lo;
-  const uint32_t ilo = a.ioff[d], ni = a.ioff[d + 1] - ilo;
-  const uint32_t ntl = (nv + kWave - 1) / kWave;
-  const uint32_t total = ntl + ni;
+  const int32_t other = FORWARD ? d - 1 : d + 1;
+  // pull reads the lists of level d, push the other lists of the other level
+  const unsigned long long pull_cost = FORWARD ? a.gin.esum[d] : a.gout.esum[d];
+  const unsigned long long push_cost = FORWARD ? a.gout.esum[other] : a.gin.esum[other];
+  const bool push = kPushWeight * push_cost < pull_cost;
+  const bool use_in = FORWARD != push;  // pull forward / push backward read in-lists
+  const GroupView &gv = use_in ? a.gin : a.gout;
+  const int64_t *rp = use_in ? a.rp_in : a.rp_out;
+  const int32_t *col = use_in ? a.col_in : a.col_out;
+  const int32_t td = push ? other : d;  // the level whose lists are read
+  uint64_t *bm_level = a.bms + (int64_t)(d & 3) * a.nwords;
+  const uint64_t *bm_other = a.bms + (int64_t)(other & 3) * a.nwords;
+  const uint64_t *probe = push ? bm_level : bm_other;
+
+  // side work: mark the next level (zeroing its state on the way out),
+  // clear the bitmap two levels on
+  {
+    const int32_t nxt = FORWARD ? d + 1 : d - 1;
+    const int64_t stride = (int64_t)gridDim.x * kBcBlock;
+    const int64_t tid = blockIdx.x * (int64_t)kBcBlock + threadIdx.x;
+    // two levels on in either direction: (d + 2) mod 4 == (d - 2) mod 4
+    uint64_t *bm_clear = a.bms + (int64_t)((d + 2) & 3) * a.nwords;
+    for (int64_t w = tid; w < a.nwords; w += stride) bm_clear[w] = 0ull;
+    if (nxt >= 1 && nxt <= a.dmax) {
+      uint64_t *bm_next = a.bms + (int64_t)(nxt & 3) * a.nwords;
+      const uint32_t lo = a.gin.off[nxt * kClasses], hi = a.gin.off[(nxt + 1) * kClasses];
+      for (int64_t i = lo + tid; i < hi; i += stride) {
+        const int32_t v = a.gin.order[i];
+        mark(bm_next, v);
+        if (FORWARD) a.ps[v] = PathState{0.0, 0.0};
+      }
+    }
+  }
+
+  uint32_t first[kClasses + 1];  // first task of each class; items last
+  uint32_t t0 = 0;
+#pragma unroll
+  for (int c = 0; c < kGroupClasses; ++c) {
+    first[c] = t0;
+    const uint32_t cnt = gv.off[td * kClasses + c + 1] - gv.off[td * kClasses + c];
+    t0 += (cnt + (kWave >> c) - 1) / (kWave >> c);
+  }
+  first[kGroupClasses] = t0;
+  const uint32_t ilo = gv.ioff[td];
+  const uint32_t total = t0 + (gv.ioff[td + 1] - ilo);
   const int lane = lane_id();
   const uint32_t nw = gridDim.x * (kBcBlock / kWave);
-  const int32_t want = FORWARD ? d - 1 : d + 1;
   for (uint32_t t = blockIdx.x * (kBcBlock / kWave) + threadIdx.x / kWave; t < total; t += nw) {
-    if (t < ntl) {
-      const uint32_t i = t * kWave + lane;
-      int32_t v = -1;
-      int64_t beg = 0;
-      int32_t deg = 0;
-      if (i < nv) {
-        v = a.order[lo + i];
-        beg = a.rp[v];
-        deg = (int32_t)(a.rp[v + 1] - beg);
-        if (deg > kLight) v = -1;  // covered by its chunk items
+    int32_t v = -1;
+    int64_t beg = 0, end = 0, step = 0;
+    int gshift = 6;
+    bool lead = false;
+    if (t < first[kGroupClasses]) {
+      int c = 0;
+      while (c + 1 < kGroupClasses && t >= first[c + 1]) ++c;
+      gshift = c;  // 1 << c lanes per vertex
+      const uint32_t lo = gv.off[td * kClasses + c];
+      const uint32_t cnt = gv.off[td * kClasses + c + 1] - lo;
+      const uint32_t vi = (t - first[c]) * (uint32_t)(kWave >> gshift) + (uint32_t)(lane >> gshift);
+      const int gi = lane & ((1 << gshift) - 1);
+      if (vi < cnt) {
+        v = gv.order[lo + vi];
+        beg = rp[v] + gi;
+        end = rp[v + 1];
+        lead = gi == 0;
       }
-      if (v < 0) continue;
-      double acc = 0.0;
-      for (int k = 0; k < deg; k += 4) {
-        int32_t u[4];
+      step = (int64_t)1 << gshift;
+    } else {
+      const int2 it = gv.items[ilo + (t - first[kGroupClasses])];
+      v = it.x;
+      const int64_t rb = rp[v] + (int64_t)it.y * kChunk;
+      beg = rb + lane;
+      end = min(rb + (int64_t)kChunk, rp[v + 1]);
+      lead = lane == 0;
+      step = kWave;
+    }
+    constexpr int R = kPerLane;  // items: kPerLane rounds; groups use the first 4
+    const int rounds = gshift < 6 ? 4 : R;
+    int32_t u[R];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) u[j] = k + j < deg ? a.col[beg + k + j] : -1;
-        bool hit[4];
+    for (int j = 0; j < R; ++j) {
+      const int64_t e = beg + j * step;
+      u[j] = (j < rounds && e < end) ? col[e] : -1;
+    }
+    bool hit[R];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) hit[j] = u[j] >= 0 && a.depth[u[j]] == want;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (!hit[j]) continue;
-          if (FORWARD) {
-            acc += a.ps[u[j]].sigma;
-          } else {
-            const PathState q = a.ps[u[j]];
-            acc += 1.0 / q.sigma + q.s;
-          }
+    for (int j = 0; j < R; ++j) hit[j] = u[j] >= 0 && in_bitmap(probe, u[j]);
+    if (push) {
+      // every lane of the group holds the pushed value of its vertex
+      double val = 0.0;
+      if (v >= 0) {
+        if (FORWARD) {
+          val = a.ps[v].sigma;
+        } else {
+          const PathState q = a.ps[v];
+          val = 1.0 / q.sigma + q.s;
         }
       }
-      if (FORWARD)
-        a.ps[v].sigma = acc;
-      else
-        a.ps[v].s = acc;
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if (hit[j]) unsafeAtomicAdd(FORWARD ? &a.ps[u[j]].sigma : &a.ps[u[j]].s, val);
     } else {
-      const int2 it = a.items[ilo + (t - ntl)];
-      const int32_t v = it.x;
-      const int64_t beg = a.rp[v] + (int64_t)it.y * kChunk;
-      const int64_t end = min(beg + (int64_t)kChunk, a.rp[v + 1]);
-      int32_t u[kPerLane];
-#pragma unroll
-      for (int j = 0; j < kPerLane; ++j) {
-        const int64_t e = beg + j * kWave + lane;
-        u[j] = e < end ? a.col[e] : -1;
-      }
-      bool hit[kPerLane];
-#pragma unroll
-      for (int j = 0; j < kPerLane; ++j) hit[j] = u[j] >= 0 && a.depth[u[j]] == want;
       double acc = 0.0;
 #pragma unroll
-      for (int j = 0; j < kPerLane; ++j) {
+      for (int j = 0; j < R; ++j) {
         if (!hit[j]) continue;
         if (FORWARD) {
           acc += a.ps[u[j]].sigma;
@@ -237,22 +341,50 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_level(LevelArgs a, int32_t d) {
           acc += 1.0 / q.sigma + q.s;
         }
       }
-      acc = wave_sum_f64(acc);
-      if (lane == 0 && acc != 0.0) unsafeAtomicAdd(FORWARD ? &a.ps[v].sigma : &a.ps[v].s, acc);
+      for (int o = (1 << gshift) >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+      if (lead) {
+        if (gshift < 6) {  // the whole list: store
+          if (FORWARD)
+            a.ps[v].sigma = acc;
+          else
+            a.ps[v].s = acc;
+        } else if (acc != 0.0) {  // one chunk of a long list
+          unsafeAtomicAdd(FORWARD ? &a.ps[v].sigma : &a.ps[v].s, acc);
+        }
+      }
     }
   }
 }
 
-// score[v] += sigma[v] * S[v] for the reached vertices after the source.
-__global__ __launch_bounds__(kBcBlock) void k_bc_accumulate(const int32_t *__restrict__ order,
-                                                            const uint32_t *__restrict__ off,
-                                                            int32_t dmax, const PathState *__restrict__ ps,
+// Level 0 and level 1 set up for the forward pass: sigma[s] = 1, s marked
+// in bitmap 0; level 1 marked in bitmap 1 with zero state.
+__global__ __launch_bounds__(kBcBlock) void k_bc_first(LevelArgs a, int32_t src) {
+  const int64_t tid = blockIdx.x * (int64_t)kBcBlock + threadIdx.x;
+  if (tid == 0) {
+    a.ps[src] = PathState{1.0, 0.0};
+    mark(a.bms, src);
+  }
+  if (a.dmax < 1) return;
+  uint64_t *bm1 = a.bms + a.nwords;
+  const uint32_t lo = a.gin.off[kClasses], hi = a.gin.off[2 * kClasses];
+  for (int64_t i = lo + tid; i < hi; i += (int64_t)gridDim.x * kBcBlock) {
+    const int32_t v = a.gin.order[i];
+    mark(bm1, v);
+    a.ps[v] = PathState{0.0, 0.0};
+  }
+}
+
+// score[v] += sigma[v] * S[v] for the reached vertices other than the source
+// (depth >= 1), in vertex order.
+__global__ __launch_bounds__(kBcBlock) void k_bc_accumulate(int64_t n, const int32_t *__restrict__ depth,
+                                                            const PathState *__restrict__ ps,
                                                             double *__restrict__ score) {
-  const uint32_t lo = off[1], hi = off[dmax + 1];
-  for (uint32_t i = lo + blockIdx.x * kBcBlock + threadIdx.x; i < hi; i += gridDim.x * kBcBlock) {
-    const int32_t v = order[i];
-    const PathState q = ps[v];
-    score[v] += q.sigma * q.s;
+  for (int64_t v = blockIdx.x * (int64_t)kBcBlock + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kBcBlock) {
+    if (depth[v] >= 1) {
+      const PathState q = ps[v];
+      score[v] += q.sigma * q.s;
+    }
   }
 }
 
@@ -263,8 +395,7 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_max(int64_t n, const double *__
   for (int64_t v = blockIdx.x * (int64_t)kBcBlock + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * kBcBlock)
     m = max(m, (unsigned long long)__double_as_longlong(score[v]));
-  for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o, kWave));
-  if (lane_id() == 0 && m) atomicMax(top, m);
+  block_max_to(m, top);
 }
 
 __global__ __launch_bounds__(kBcBlock) void k_bc_scale(int64_t n, double *__restrict__ score,
@@ -290,6 +421,68 @@ T *carve(char *&p, size_t count) {
 
 }  // namespace
 
+// Vertices of one search grouped by (depth, class of the given lists) and
+// the chunk items of the long lists, per depth.
+struct Grouping {
+  int32_t *order;
+  int2 *items;
+  uint32_t *cnt, *icnt;  // counts, then cursors
+  uint32_t *off, *ioff;  // their exclusive scans
+  unsigned long long *esum;
+};
+
+static gap_status build_grouping(const Grouping &gr, int64_t n, int32_t max_depth,
+                                 const int32_t *depth, const int64_t *rp, size_t nk, size_t nl,
+                                 void *scan_tmp, size_t scan_bytes, int grid_tiles,
+                                 hipStream_t stream) {
+  GAP_HIP(hipMemsetAsync(gr.cnt, 0, nk * sizeof(uint32_t), stream));
+  GAP_HIP(hipMemsetAsync(gr.icnt, 0, nl * sizeof(uint32_t), stream));
+  GAP_HIP(hipMemsetAsync(gr.esum, 0, nl * sizeof(unsigned long long), stream));
+  GroupArgs ga{n, max_depth, depth, rp, gr.cnt, gr.icnt, gr.esum, gr.order, gr.items};
+  k_bc_count<<<grid_tiles, kBcBlock, 0, stream>>>(ga);
+  GAP_HIP(hipGetLastError());
+  GAP_HIP(rocprim::exclusive_scan(scan_tmp, scan_bytes, gr.cnt, gr.off, 0u, nk,
+                                  rocprim::plus<uint32_t>(), stream));
+  GAP_HIP(rocprim::exclusive_scan(scan_tmp, scan_bytes, gr.icnt, gr.ioff, 0u, nl,
+                                  rocprim::plus<uint32_t>(), stream));
+  // the counts become cursors starting at each bin's first slot
+  GAP_HIP(hipMemcpyAsync(gr.cnt, gr.off, nk * sizeof(uint32_t), hipMemcpyDeviceToDevice, stream));
+  GAP_HIP(hipMemcpyAsync(gr.icnt, gr.ioff, nl * sizeof(uint32_t), hipMemcpyDeviceToDevice, stream));
+  k_bc_scatter<<<grid_tiles, kBcBlock, 0, stream>>>(ga);
+  GAP_HIP(hipGetLastError());
+  return GAP_OK;
+}
+
+// Per-depth arrays of the groupings for searches of at most max_depth
+// levels, carved from the workspace.
+static gap_status groupings_for(Workspace *ws, int32_t max_depth, int ngroup, Grouping *gr,
+                                size_t vbytes, size_t *nk, size_t *nl, void **scan_tmp,
+                                size_t *scan_bytes, hipStream_t stream) {
+  *nk = (size_t)(max_depth + 1) * kClasses + 1;
+  *nl = (size_t)max_depth + 2;
+  auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+  *scan_bytes = 0;
+  GAP_HIP(rocprim::exclusive_scan(nullptr, *scan_bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                  0u, *nk, rocprim::plus<uint32_t>(), stream));
+  gap_status st = workspace_reserve_bc(
+      ws, vbytes, ngroup * (2 * al(4 * *nk) + 2 * al(4 * *nl) + al(8 * *nl)) + *scan_bytes + 256);
+  if (st != GAP_OK) return st;
+  char *q = reinterpret_cast<char *>(ws->bc_lv);
+  for (int i = 0; i < ngroup; ++i) {
+    gr[i].cnt = carve<uint32_t>(q, *nk);
+    gr[i].off = carve<uint32_t>(q, *nk);
+    gr[i].icnt = carve<uint32_t>(q, *nl);
+    gr[i].ioff = carve<uint32_t>(q, *nl);
+    gr[i].esum = carve<unsigned long long>(q, *nl);
+  }
+  *scan_tmp = q;
+  return GAP_OK;
+}
+
+// Searches up to this depth are grouped before the host knows the depth
+// (the read-back overlaps the grouping); deeper ones are grouped again.
+constexpr int32_t kPresizedDepth = 254;
+
 gap_status run_bc(const gap_graph *g, const int32_t *sources, int32_t num_sources, double *score,
                   bool normalise, hipStream_t stream) {
   const DeviceInfo *di = nullptr;
@@ -301,26 +494,32 @@ gap_status run_bc(const gap_graph *g, const int32_t *sources, int32_t num_source
     return GAP_ENOMEM;
   }
   const int64_t n = g->n;
+  const int64_t nwords = (n + 63) / 64;
   const bool directed = g->directed != 0;
+  const int ngroup = directed ? 2 : 1;  // in-lists, and out-lists when they differ
   // chunk items: sum over long lists of ceil(deg / kChunk)
-  const int64_t cap_items = g->nnz / kChunk + g->nnz / (kLight + 1) + 1;
-  const size_t vbytes = 4 * 256 + sizeof(int32_t) * 3 * (size_t)n + sizeof(PathState) * (size_t)n +
-                        sizeof(int2) * (size_t)cap_items * (directed ? 2 : 1) + 6 * 256;
+  const int64_t cap_items = g->nnz / kChunk + g->nnz / (kLong + 1) + 1;
+  const size_t vbytes = 16 * 256 + sizeof(int32_t) * (2 + ngroup) * (size_t)n +
+                        sizeof(PathState) * (size_t)n + sizeof(uint64_t) * 4 * (size_t)nwords +
+                        sizeof(int2) * (size_t)cap_items * ngroup;
   st = workspace_reserve_bc(ws, vbytes, 0);
   if (st != GAP_OK) return st;
   char *p = reinterpret_cast<char *>(ws->bc_buf);
   int32_t *depth = carve<int32_t>(p, n);
   int32_t *parent = carve<int32_t>(p, n);
-  int32_t *order = carve<int32_t>(p, n);
   PathState *ps = carve<PathState>(p, n);
-  int2 *items_in = carve<int2>(p, cap_items);
-  int2 *items_out = directed ? carve<int2>(p, cap_items) : items_in;
+  uint64_t *bms = carve<uint64_t>(p, 4 * nwords);
+  Grouping gr[2];
+  for (int i = 0; i < ngroup; ++i) {
+    gr[i].order = carve<int32_t>(p, n);
+    gr[i].items = carve<int2>(p, cap_items);
+  }
   int32_t *dmax_d = carve<int32_t>(p, 1);
   unsigned long long *top_d = carve<unsigned long long>(p, 1);
 
   GAP_HIP(hipMemsetAsync(score, 0, sizeof(double) * (size_t)n, stream));
   const gap_params bp = params_current();
-  const int grid_v = blocks_for(n, di->cus * 16);
+  const int grid_v = blocks_for(n, di->cus * 4);
   const int grid_lv = di->cus * 8;
   const int grid_tiles = (int)((n + kTile - 1) / kTile);
   for (int32_t k = 0; k < num_sources; ++k) {
@@ -328,57 +527,47 @@ gap_status run_bc(const gap_graph *g, const int32_t *sources, int32_t num_source
     st = run_bfs(g, s, parent, depth, stream, bp, nullptr, 0, nullptr);
     if (st != GAP_OK) return st;
     GAP_HIP(hipMemsetAsync(dmax_d, 0, sizeof(int32_t), stream));
-    k_bc_init<<<grid_v, kBcBlock, 0, stream>>>(n, depth, s, ps, dmax_d);
+    k_bc_start<<<grid_v, kBcBlock, 0, stream>>>(n, depth, bms, dmax_d);
     GAP_HIP(hipGetLastError());
+    // the depth travels to the host while the grouping (sized for
+    // kPresizedDepth levels) runs
     int32_t *h = reinterpret_cast<int32_t *>(ws->bc_host);
     GAP_HIP(hipMemcpyAsync(h, dmax_d, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    GAP_HIP(hipStreamSynchronize(stream));
+    GAP_HIP(hipEventRecord(ws->bc_event, stream));
+    const int32_t cap = (int32_t)std::min<int64_t>(kPresizedDepth, n - 1);
+    size_t nk = 0, nl = 0, scan_bytes = 0;
+    void *scan_tmp = nullptr;
+    st = groupings_for(ws, cap, ngroup, gr, vbytes, &nk, &nl, &scan_tmp, &scan_bytes, stream);
+    if (st != GAP_OK) return st;
+    for (int i = 0; i < ngroup; ++i) {
+      st = build_grouping(gr[i], n, cap, depth, i == 0 ? g->row_ptr_in : g->row_ptr, nk, nl,
+                          scan_tmp, scan_bytes, grid_tiles, stream);
+      if (st != GAP_OK) return st;
+    }
+    GAP_HIP(hipEventSynchronize(ws->bc_event));
     const int32_t D = h[0];
     if (D < 0 || D >= n) {
       set_error("gap_bc: inconsistent depth %d after the search", D);
       return GAP_EINTERNAL;
     }
-    // per-depth arrays: counts (then cursors) and their scans, D + 2 entries
-    const size_t nl = (size_t)D + 2;
-    size_t scan_bytes = 0;
-    GAP_HIP(rocprim::exclusive_scan(nullptr, scan_bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                    0u, nl, rocprim::plus<uint32_t>(), stream));
-    st = workspace_reserve_bc(ws, vbytes,
-                              6 * ((nl * sizeof(uint32_t) + 255) & ~(size_t)255) + scan_bytes + 256);
-    if (st != GAP_OK) return st;
-    char *q = reinterpret_cast<char *>(ws->bc_lv);
-    uint32_t *cnt = carve<uint32_t>(q, nl);
-    uint32_t *icnt_in = carve<uint32_t>(q, nl);
-    uint32_t *icnt_out = carve<uint32_t>(q, nl);
-    uint32_t *off = carve<uint32_t>(q, nl);
-    uint32_t *ioff_in = carve<uint32_t>(q, nl);
-    uint32_t *ioff_out = directed ? carve<uint32_t>(q, nl) : ioff_in;
-    void *scan_tmp = q;
-    GAP_HIP(hipMemsetAsync(cnt, 0, 3 * ((nl * sizeof(uint32_t) + 255) & ~(size_t)255), stream));
-    GroupArgs ga{n, depth, g->row_ptr_in, directed ? g->row_ptr : nullptr, cnt, icnt_in, icnt_out,
-                 order, items_in, items_out};
-    k_bc_count<<<grid_tiles, kBcBlock, 0, stream>>>(ga);
-    GAP_HIP(hipGetLastError());
-    GAP_HIP(rocprim::exclusive_scan(scan_tmp, scan_bytes, cnt, off, 0u, nl,
-                                    rocprim::plus<uint32_t>(), stream));
-    GAP_HIP(rocprim::exclusive_scan(scan_tmp, scan_bytes, icnt_in, ioff_in, 0u, nl,
-                                    rocprim::plus<uint32_t>(), stream));
-    if (directed)
-      GAP_HIP(rocprim::exclusive_scan(scan_tmp, scan_bytes, icnt_out, ioff_out, 0u, nl,
-                                      rocprim::plus<uint32_t>(), stream));
-    // the counts become cursors starting at each level's first slot
-    GAP_HIP(hipMemcpyAsync(cnt, off, nl * sizeof(uint32_t), hipMemcpyDeviceToDevice, stream));
-    GAP_HIP(hipMemcpyAsync(icnt_in, ioff_in, nl * sizeof(uint32_t), hipMemcpyDeviceToDevice, stream));
-    if (directed)
-      GAP_HIP(hipMemcpyAsync(icnt_out, ioff_out, nl * sizeof(uint32_t), hipMemcpyDeviceToDevice,
-                             stream));
-    k_bc_scatter<<<grid_tiles, kBcBlock, 0, stream>>>(ga);
-    GAP_HIP(hipGetLastError());
-    LevelArgs fa{order, off, items_in, ioff_in, g->row_ptr_in, g->col_in, depth, ps};
-    for (int32_t d = 1; d <= D; ++d) k_bc_level<true><<<grid_lv, kBcBlock, 0, stream>>>(fa, d);
-    LevelArgs ba{order, off, items_out, ioff_out, g->row_ptr, g->col, depth, ps};
-    for (int32_t d = D - 1; d >= 0; --d) k_bc_level<false><<<grid_lv, kBcBlock, 0, stream>>>(ba, d);
-    k_bc_accumulate<<<grid_v, kBcBlock, 0, stream>>>(order, off, D, ps, score);
+    if (D > cap) {  // a deep search: group again with room for every level
+      st = groupings_for(ws, D, ngroup, gr, vbytes, &nk, &nl, &scan_tmp, &scan_bytes, stream);
+      if (st != GAP_OK) return st;
+      for (int i = 0; i < ngroup; ++i) {
+        st = build_grouping(gr[i], n, D, depth, i == 0 ? g->row_ptr_in : g->row_ptr, nk, nl,
+                            scan_tmp, scan_bytes, grid_tiles, stream);
+        if (st != GAP_OK) return st;
+      }
+    }
+    const Grouping &gi = gr[0], &go = gr[ngroup - 1];
+    LevelArgs la{GroupView{gi.order, gi.off, gi.items, gi.ioff, gi.esum},
+                 GroupView{go.order, go.off, go.items, go.ioff, go.esum},
+                 g->row_ptr_in, g->row_ptr, g->col_in, g->col, bms, nwords, D, ps};
+    k_bc_first<<<grid_v, kBcBlock, 0, stream>>>(la, s);
+    for (int32_t d = 1; d <= D; ++d) k_bc_level<true><<<grid_lv, kBcBlock, 0, stream>>>(la, d);
+    // the source's own S is never used
+    for (int32_t d = D - 1; d >= 1; --d) k_bc_level<false><<<grid_lv, kBcBlock, 0, stream>>>(la, d);
+    k_bc_accumulate<<<grid_v, kBcBlock, 0, stream>>>(n, depth, ps, score);
     GAP_HIP(hipGetLastError());
   }
   if (normalise) {

@@ -92,6 +92,7 @@ struct Workspace {
   size_t bc_lv_bytes = 0;
   void *bc_lv = nullptr;
   void *bc_host = nullptr;  // pinned, 256 bytes
+  hipEvent_t bc_event = nullptr;  // marks the depth read-back
 };
 
 Workspace *workspace_for(int dev, hipStream_t stream);

@@ -2,8 +2,8 @@
 times: R-MAT scale 22 and uniform-random 2^22 (single-source and the
 64-lane batch), the 4096^2 road-like grid (persistent kernel and captured
 level graphs), R-MAT scale 24 in batches of 64 and 256 lanes, the mixed
-batch of 16 R-MAT graphs of scales 14-20, and R-MAT scale 22 taken as a
-directed graph.
+batch of 16 R-MAT graphs of scales 14-20, R-MAT scale 22 taken as a
+directed graph, and betweenness centrality on R-MAT scale 22.
 
 Sampled searches are checked in full against the oracle (depths bit-exact,
 parents valid, Section 2.1).  Every lane of a large batch is also checked
@@ -214,3 +214,35 @@ def test_fullsize_rmat22_directed(gpu):
                 p, d = run_single(g, srcs[i], params=sch)
                 assert_valid(A, srcs[i], p, d, ref, what=f"{name} {sch}")
     g.free()
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_bc_rmat22(gpu):
+    """Betweenness centrality on R-MAT 22 from 4 sources (the benchmark's
+    trial), every score against the oracle (|gpu - oracle| <= 1e-9 |oracle|
+    + 1e-12 max), and one source's raw scores against the identity
+    sum = total of (distance - 1) over the reached vertices."""
+    import torch
+    from paper_1508_03619_amd import inputs, gapbfs as gb
+    name = "rmat22"
+    srcs = [int(x) for x in inputs.pick_sources(workload(name)["el"], 32,
+                                                seed=inputs.SOURCE_SEEDS[name] + 5)][:4]
+    g = workload(name)["g"]
+    A = adjacency(name)
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    say(f"{name}: betweenness from {srcs}")
+    gb.bc(g, srcs, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    say(f"{name}: oracle betweenness")
+    ref = A.bc(srcs)
+    tol = 1e-9 * np.abs(ref) + 1e-12 * float(ref.max())
+    bad = np.nonzero(~(np.abs(got - ref) <= tol))[0]
+    assert bad.size == 0, (bad.size, int(bad[0]), got[bad[0]], ref[bad[0]])
+    gb.bc(g, srcs[:1], out, normalise=False)
+    torch.cuda.synchronize()
+    raw = out.cpu().numpy()
+    depth = A.bfs(srcs[0])[0]
+    want = float(np.sum(depth[depth > 0] - 1))
+    assert abs(raw.sum() - want) <= 1e-9 * want
+    drop(name)
