@@ -24,8 +24,8 @@
 // vertex of the neighbouring level adds its value atomically to the
 // neighbours that lie in the level: out-lists for sigma, in-lists for S),
 // whichever reads fewer adjacency entries -- the direction choice of the
-// paper's BFS applied to the two passes of Brandes' method (pushes are
-// charged twice for their atomics).
+// paper's BFS applied to the two passes of Brandes' method (pushed entries
+// are charged four times for their atomics).
 // Finally the scores are divided by the largest one (normalised to one),
 // unless the caller asks for raw sums.
 //
@@ -52,7 +52,11 @@ constexpr int kClasses = kGroupClasses + 1;  // the last class: chunk items
 constexpr int kLong = 4 << (kGroupClasses - 1);  // 128: longer lists become chunk items
 constexpr int kChunk = 512;     // entries per chunk item
 constexpr int kPerLane = kChunk / kWave;
-constexpr unsigned long long kPushWeight = 2;  // an atomic update costs about two probes
+// A pushed entry costs about four probed ones: device-scope atomics are
+// carried out at the memory side, not in the L2 (measured on the levels of
+// R-MAT and uniform graphs of scale 22).
+constexpr unsigned long long kPushWeight = 4;
+constexpr int kWaves = kBcBlock / kWave;
 
 // Per-vertex state read together by the level below: one 16-byte load.
 struct __align__(16) PathState {
@@ -274,10 +278,16 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_level(LevelArgs a, int32_t d) {
   const uint32_t ilo = gv.ioff[td];
   const uint32_t total = t0 + (gv.ioff[td + 1] - ilo);
   const int lane = lane_id();
-  const uint32_t nw = gridDim.x * (kBcBlock / kWave);
-  for (uint32_t t = blockIdx.x * (kBcBlock / kWave) + threadIdx.x / kWave; t < total; t += nw) {
+  const int wave = threadIdx.x / kWave;
+  // partial sums of chunk items, combined per vertex inside the workgroup
+  // (a vertex's items are adjacent tasks) before one atomic update
+  __shared__ int32_t item_v[kWaves];
+  __shared__ double item_acc[kWaves];
+  // every wave of a workgroup runs the same number of rounds (barriers below)
+  for (uint32_t bt = blockIdx.x; bt * kWaves < total; bt += gridDim.x) {
+    const uint32_t t = bt * kWaves + wave;
     int32_t v = -1;
-    int64_t beg = 0, end = 0, step = 0;
+    int64_t beg = 0, end = 0, step = kWave;
     int gshift = 6;
     bool lead = false;
     if (t < first[kGroupClasses]) {
@@ -295,14 +305,13 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_level(LevelArgs a, int32_t d) {
         lead = gi == 0;
       }
       step = (int64_t)1 << gshift;
-    } else {
+    } else if (t < total) {
       const int2 it = gv.items[ilo + (t - first[kGroupClasses])];
       v = it.x;
       const int64_t rb = rp[v] + (int64_t)it.y * kChunk;
       beg = rb + lane;
       end = min(rb + (int64_t)kChunk, rp[v + 1]);
       lead = lane == 0;
-      step = kWave;
     }
     constexpr int R = kPerLane;  // items: kPerLane rounds; groups use the first 4
     const int rounds = gshift < 6 ? 4 : R;
@@ -342,16 +351,31 @@ __global__ __launch_bounds__(kBcBlock) void k_bc_level(LevelArgs a, int32_t d) {
         }
       }
       for (int o = (1 << gshift) >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-      if (lead) {
-        if (gshift < 6) {  // the whole list: store
-          if (FORWARD)
-            a.ps[v].sigma = acc;
-          else
-            a.ps[v].s = acc;
-        } else if (acc != 0.0) {  // one chunk of a long list
-          unsafeAtomicAdd(FORWARD ? &a.ps[v].sigma : &a.ps[v].s, acc);
+      if (lead && gshift < 6) {  // a whole list: store
+        if (FORWARD)
+          a.ps[v].sigma = acc;
+        else
+          a.ps[v].s = acc;
+      }
+      if (lane == 0) {
+        item_v[wave] = (gshift == 6) ? v : -1;
+        item_acc[wave] = acc;
+      }
+      __syncthreads();
+      if (threadIdx.x < kWaves) {
+        const int w = threadIdx.x;
+        const int32_t x = item_v[w];
+        bool first_of_v = x >= 0;
+        for (int k = 0; k < w; ++k)
+          if (item_v[k] == x) first_of_v = false;
+        if (first_of_v) {
+          double sum = 0.0;
+          for (int k = w; k < kWaves; ++k)
+            if (item_v[k] == x) sum += item_acc[k];
+          if (sum != 0.0) unsafeAtomicAdd(FORWARD ? &a.ps[x].sigma : &a.ps[x].s, sum);
         }
       }
+      __syncthreads();
     }
   }
 }
