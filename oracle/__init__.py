@@ -21,6 +21,9 @@ Definitions followed (the paper, arXiv 1508.03619):
     over the given sources s and all targets t, normalised so the largest
     score is one; Brandes' method without recorded successors (the paper's
     verifier for this kernel is also a serial Brandes, Section 3).
+  * Shortest paths (Section 2.1): dist[source] = 0, unreachable vertices
+    get the sentinel (-1 here), otherwise the least total weight of a path;
+    Dijkstra's algorithm, the paper's verifier for this kernel (Section 3).
 
 The C implementation is ``oracle.c``; ``build()`` compiles it with gcc.
 """
@@ -77,6 +80,11 @@ def _bind(path: str):
     lib.oracle_bc.argtypes = [ctypes.c_int64, i64p, i32p, ctypes.c_int32, i32p, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_double)]
     lib.oracle_bc.restype = ctypes.c_int
+    lib.oracle_build_weighted_adjacency.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i32p,
+                                                    ctypes.c_int, i64p, i32p, i32p]
+    lib.oracle_build_weighted_adjacency.restype = ctypes.c_int64
+    lib.oracle_sssp.argtypes = [ctypes.c_int64, i64p, i32p, i32p, ctypes.c_int32, i64p]
+    lib.oracle_sssp.restype = ctypes.c_int64
     return lib
 
 
@@ -163,6 +171,40 @@ class Adjacency:
         """Undirected edges inside the reached set: half the degree sum."""
         deg = self.degree()
         return int(deg[np.asarray(depth) >= 0].sum()) // 2
+
+
+class WeightedAdjacency:
+    """Weighted adjacency built by the oracle from raw (src, dst, weight)
+    triples: undirected by default, out-lists with ``directed=True``; a
+    repeated pair keeps its smallest weight."""
+
+    def __init__(self, n: int, src, dst, w, _lib=None, directed: bool = False):
+        L = _lib or lib()
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        w = np.ascontiguousarray(w, dtype=np.int32)
+        m = int(src.shape[0])
+        self.n = int(n)
+        self.offsets = np.zeros(self.n + 1, dtype=np.int64)
+        cap = max((m if directed else 2 * m), 1)
+        adj = np.empty(cap, dtype=np.int32)
+        wadj = np.empty(cap, dtype=np.int32)
+        nnz = L.oracle_build_weighted_adjacency(self.n, m, _i32(src), _i32(dst), _i32(w),
+                                                1 if directed else 0, _i64(self.offsets),
+                                                _i32(adj), _i32(wadj))
+        if nnz < 0:
+            raise ValueError("oracle_build_weighted_adjacency: bad input")
+        self.adj = adj[:nnz].copy()
+        self.wadj = wadj[:nnz].copy()
+        self._lib = L
+
+    def sssp(self, source: int) -> np.ndarray:
+        """int64 distances, -1 when unreachable (Dijkstra)."""
+        dist = np.empty(self.n, dtype=np.int64)
+        if self._lib.oracle_sssp(self.n, _i64(self.offsets), _i32(self.adj), _i32(self.wadj),
+                                 int(source), _i64(dist)) < 0:
+            raise ValueError("oracle_sssp: bad input")
+        return dist
 
 
 def components(n: int, src: np.ndarray, dst: np.ndarray, _lib=None) -> np.ndarray:

@@ -1,6 +1,6 @@
 /*
- * CPU ORACLE FOR BREADTH-FIRST SEARCH AND BETWEENNESS CENTRALITY --
- * TEST INFRASTRUCTURE ONLY.
+ * CPU ORACLE FOR BREADTH-FIRST SEARCH, BETWEENNESS CENTRALITY AND
+ * SINGLE-SOURCE SHORTEST PATHS -- TEST INFRASTRUCTURE ONLY.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * use this file.  It shares no code with the GPU library: it builds its own
@@ -22,6 +22,9 @@
  *
  * Betweenness centrality (Section 2.1): Brandes' dependency accumulation
  * from a set of sources, normalised by the largest score; see oracle_bc.
+ * Shortest paths (Section 2.1): distances by Dijkstra's algorithm (the
+ * paper's verifier for this kernel, Section 3) over a weighted adjacency
+ * in which a repeated pair keeps its smallest weight; see oracle_sssp.
  *
  * Pins (tests): exhaustive small graphs against Floyd-Warshall and boolean
  * matrix powers, random graphs against scipy's csgraph, closed forms (path,
@@ -30,7 +33,10 @@
  * enumerated on small graphs (the definition itself), closed forms (path,
  * star, cycle, complete graph), and the identity that a source's
  * dependencies sum to the total of (distance - 1) over the vertices it
- * reaches.
+ * reaches.  Shortest paths: Floyd-Warshall on small weighted graphs,
+ * scipy's Dijkstra, unit weights against the BFS depths, closed forms, and
+ * the two properties that define the answer (no edge can shorten a
+ * distance; every reached vertex has an edge that attains it).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -362,4 +368,146 @@ int oracle_bc(int64_t n, const int64_t *offsets, const int32_t *adj,
   free(sigma);
   free(delta);
   return 0;
+}
+
+/* ---- single-source shortest paths (Section 2.1, "SSSP") ----------------- */
+
+typedef struct {
+  int32_t v;
+  int32_t w;
+} wentry;
+
+static int cmp_wentry(const void *a, const void *b) {
+  const wentry *x = (const wentry *)a, *y = (const wentry *)b;
+  if (x->v != y->v) return (x->v > y->v) - (x->v < y->v);
+  return (x->w > y->w) - (x->w < y->w);
+}
+
+/*
+ * Weighted adjacency: undirected (every pair in both directions) or, with
+ * directed != 0, out-lists; self-loops dropped; a pair given several times
+ * keeps its smallest weight.  offsets: int64[n+1]; adj, wadj: capacity
+ * 2*m (undirected) or m.  Weights must be >= 1.  Returns nnz, or -1.
+ */
+int64_t oracle_build_weighted_adjacency(int64_t n, int64_t m, const int32_t *src,
+                                        const int32_t *dst, const int32_t *w,
+                                        int directed, int64_t *offsets,
+                                        int32_t *adj, int32_t *wadj) {
+  if (n <= 0 || m < 0 || !offsets || (m > 0 && (!src || !dst || !w || !adj || !wadj)))
+    return -1;
+  for (int64_t v = 0; v <= n; ++v) offsets[v] = 0;
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || u >= n || v >= n || w[e] < 1) return -1;
+    if (u == v) continue;
+    offsets[u + 1] += 1;
+    if (!directed) offsets[v + 1] += 1;
+  }
+  for (int64_t v = 0; v < n; ++v) offsets[v + 1] += offsets[v];
+  wentry *tmp = (wentry *)malloc(sizeof(wentry) * (size_t)(offsets[n] > 0 ? offsets[n] : 1));
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!tmp || !fill) {
+    free(tmp);
+    free(fill);
+    return -1;
+  }
+  for (int64_t v = 0; v < n; ++v) fill[v] = offsets[v];
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t u = src[e], v = dst[e];
+    if (u == v) continue;
+    tmp[fill[u]].v = v;
+    tmp[fill[u]++].w = w[e];
+    if (!directed) {
+      tmp[fill[v]].v = u;
+      tmp[fill[v]++].w = w[e];
+    }
+  }
+  int64_t out = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t start = offsets[v], end = offsets[v + 1];
+    qsort(tmp + start, (size_t)(end - start), sizeof(wentry), cmp_wentry);
+    offsets[v] = out;
+    for (int64_t i = start; i < end; ++i) {
+      if (i > start && tmp[i].v == tmp[i - 1].v) continue; /* heavier repeat */
+      adj[out] = tmp[i].v;
+      wadj[out] = tmp[i].w;
+      ++out;
+    }
+  }
+  offsets[n] = out;
+  free(tmp);
+  free(fill);
+  return out;
+}
+
+/* binary min-heap of (distance, vertex) with lazy deletion */
+typedef struct {
+  int64_t d;
+  int32_t v;
+} hitem;
+
+static void heap_push(hitem *h, int64_t *size, int64_t d, int32_t v) {
+  int64_t i = (*size)++;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h[p].d <= d) break;
+    h[i] = h[p];
+    i = p;
+  }
+  h[i].d = d;
+  h[i].v = v;
+}
+
+static hitem heap_pop(hitem *h, int64_t *size) {
+  hitem top = h[0], last = h[--(*size)];
+  int64_t i = 0;
+  for (;;) {
+    int64_t c = 2 * i + 1;
+    if (c >= *size) break;
+    if (c + 1 < *size && h[c + 1].d < h[c].d) ++c;
+    if (h[c].d >= last.d) break;
+    h[i] = h[c];
+    i = c;
+  }
+  if (*size > 0) h[i] = last;
+  return top;
+}
+
+/*
+ * Dijkstra's algorithm from source over (offsets, adj, wadj): dist[v] is the
+ * least total weight of a path from the source, -1 when v is unreachable.
+ * Returns the number of reached vertices, or -1 on bad input.
+ */
+int64_t oracle_sssp(int64_t n, const int64_t *offsets, const int32_t *adj,
+                    const int32_t *wadj, int32_t source, int64_t *dist) {
+  if (n <= 0 || source < 0 || source >= n || !offsets || !dist) return -1;
+  const int64_t nnz = offsets[n];
+  hitem *h = (hitem *)malloc(sizeof(hitem) * (size_t)(nnz + 1));
+  char *done = (char *)calloc((size_t)n, 1);
+  if (!h || !done) {
+    free(h);
+    free(done);
+    return -1;
+  }
+  for (int64_t v = 0; v < n; ++v) dist[v] = -1;
+  int64_t size = 0, reached = 0;
+  dist[source] = 0;
+  heap_push(h, &size, 0, source);
+  while (size > 0) {
+    hitem it = heap_pop(h, &size);
+    if (done[it.v]) continue;
+    done[it.v] = 1;
+    ++reached;
+    for (int64_t i = offsets[it.v]; i < offsets[it.v + 1]; ++i) {
+      const int32_t v = adj[i];
+      const int64_t nd = it.d + wadj[i];
+      if (!done[v] && (dist[v] < 0 || nd < dist[v])) {
+        dist[v] = nd;
+        heap_push(h, &size, nd, v);
+      }
+    }
+  }
+  free(h);
+  free(done);
+  return reached;
 }

@@ -61,6 +61,8 @@ def _load():
         lib.gapgen_pick_sources.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p,
                                             ctypes.c_uint64, ctypes.c_int32, i32p]
         lib.gapgen_pick_sources.restype = ctypes.c_int32
+        lib.gapgen_weights.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_uint64, ctypes.c_int, i32p]
+        lib.gapgen_weights.restype = ctypes.c_int
         lib.gapgen_pick_out_sources.argtypes = lib.gapgen_pick_sources.argtypes
         lib.gapgen_pick_out_sources.restype = ctypes.c_int32
         lib.gapgen_set_threads.argtypes = [ctypes.c_int]
@@ -164,6 +166,16 @@ def pick_sources(el: EdgeList, k: int = 64, seed: int = 1, directed: bool = Fals
     return out[:got].copy()
 
 
+def weights(el: EdgeList, seed: int = 1, directed: bool = False) -> np.ndarray:
+    """Integer weights 1..255 per raw pair (Section 2.2), a function of the
+    pair's endpoints (unordered unless ``directed``) and the seed."""
+    w = np.empty(max(el.m, 1), dtype=np.int32)
+    if _load().gapgen_weights(int(el.m), _p(el.src), _p(el.dst), int(seed) & (2**64 - 1),
+                              1 if directed else 0, _p(w)) != 0:
+        raise ValueError("the weight generator rejected its arguments")
+    return w[:el.m].copy()
+
+
 # Named workloads (sizes and seeds of the measured configurations).
 def workload(name: str) -> EdgeList:
     """Named synthetic workloads used by the tests and the benchmark."""
@@ -187,6 +199,10 @@ def workload(name: str) -> EdgeList:
 
 SOURCE_SEEDS = {"rmat16": 1016001, "rmat22": 1022001, "urand22": 1022002,
                 "rmat24": 1024001, "grid4096": 1040960, "rmat16d": 1016003, "rmat22d": 1022003}
+
+# Seeds of the edge weights of the shortest-path workloads.
+WEIGHT_SEEDS = {"rmat16": 2016001, "rmat22": 2022001, "urand22": 2022002, "grid4096": 2040960,
+                "rmat16d": 2016003, "rmat22d": 2022003}
 
 # Workloads whose pairs are directed edges (build with directed=True, pick
 # sources with directed=True).

@@ -49,7 +49,7 @@ static inline uint32_t bounded32(uint32_t r, uint32_t bound) {
 }
 
 enum { TAG_RMAT = 1, TAG_PERM = 2, TAG_URAND = 3, TAG_GRID_DEL = 4,
-       TAG_GRID_SC = 5, TAG_SOURCES = 6 };
+       TAG_GRID_SC = 5, TAG_SOURCES = 6, TAG_WEIGHTS = 7 };
 
 void gapgen_set_threads(int t) {
 #ifdef _OPENMP
@@ -325,4 +325,28 @@ int32_t gapgen_pick_out_sources(int64_t n, int64_t m, const int32_t *src,
                                 const int32_t *dst, uint64_t seed, int32_t k,
                                 int32_t *out) {
   return pick_sources(n, m, src, dst, seed, k, out, 1);
+}
+
+
+/* Edge weights for the shortest-path kernel (Section 2.2: the unweighted
+ * graphs get uniform integer weights 1..255).  The weight of pair e is a
+ * function of its endpoints only -- of the unordered pair when undirected,
+ * of (src, dst) when directed -- so repeated pairs and the two directions
+ * of an undirected edge agree.  Returns 0, or -1 on bad input. */
+int gapgen_weights(int64_t m, const int32_t *src, const int32_t *dst,
+                   uint64_t seed, int directed, int32_t *w) {
+  if (m < 0 || (m > 0 && (!src || !dst || !w))) return -1;
+  const uint64_t key = stream_key(seed, TAG_WEIGHTS);
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m; ++e) {
+    uint32_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
+    if (!directed && a > b) {
+      uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    const uint64_t r = draw(key, ((uint64_t)a << 32) | b);
+    w[e] = 1 + (int32_t)bounded32((uint32_t)(r >> 32), 255u);
+  }
+  return 0;
 }

@@ -120,3 +120,24 @@ def test_bc_mutant_is_caught(tmp_path, name):
     from tests import test_oracle_bc as TB
     L = _compile_mutant(tmp_path, BC_MUTANTS[name])
     assert not TB.bc_pins_ok(L), f"mutant {name} passed every betweenness pin"
+
+
+# Mistakes in the weighted builder and Dijkstra, caught by the shortest-path pins.
+SSSP_MUTANTS = {
+    "sssp_keeps_heaviest_repeat": [("  return (x->w > y->w) - (x->w < y->w);",
+                                    "  return (x->w < y->w) - (x->w > y->w);")],
+    "sssp_ignores_weights": [("      const int64_t nd = it.d + wadj[i];", "      const int64_t nd = it.d + 1;")],
+    "sssp_max_heap": [("    if (h[p].d <= d) break;", "    if (h[p].d >= d) break;"),
+                      ("    if (c + 1 < *size && h[c + 1].d < h[c].d) ++c;\n    if (h[c].d >= last.d) break;",
+                       "    if (c + 1 < *size && h[c + 1].d > h[c].d) ++c;\n    if (h[c].d <= last.d) break;")],
+    "sssp_no_reverse_edge": [("    if (!directed) {\n      tmp[fill[v]].v = u;", "    if (0) {\n      tmp[fill[v]].v = u;")],
+    "sssp_first_visit_final": [("      if (!done[v] && (dist[v] < 0 || nd < dist[v])) {",
+                                "      if (!done[v] && dist[v] < 0) {")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(SSSP_MUTANTS))
+def test_sssp_mutant_is_caught(tmp_path, name):
+    from tests import test_oracle_sssp as TS
+    L = _compile_mutant(tmp_path, SSSP_MUTANTS[name])
+    assert not TS.sssp_pins_ok(L), f"mutant {name} passed every shortest-path pin"
