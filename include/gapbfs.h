@@ -82,6 +82,26 @@ gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges,
                          const int32_t *src, const int32_t *dst,
                          uint32_t flags, void *stream, gap_graph **out);
 
+/*
+ * gap_build_csr_weighted -- as gap_build_csr, with a weight per raw pair
+ * for the shortest-path kernel (Section 2.1; Section 2.2 gives unweighted
+ * graphs uniform integer weights 1..255).
+ *   weights  host int32[num_edges], each >= 1; copied.  A pair given more
+ *            than once keeps its smallest weight; for an undirected graph
+ *            both directions of a pair carry its weight.
+ * Other arguments and errors as gap_build_csr, plus GAP_EINVAL for NULL
+ * weights or a weight below 1.  The weights are stored beside the out-lists
+ * (4 bytes per entry).  Searches other than gap_sssp ignore them.
+ */
+gap_status gap_build_csr_weighted(int64_t num_vertices, int64_t num_edges,
+                                  const int32_t *src, const int32_t *dst,
+                                  const int32_t *weights, uint32_t flags,
+                                  void *stream, gap_graph **out);
+
+/* Copies the out-list weights (host int32[nnz], in gap_graph_export order).
+ * GAP_EINVAL when the graph was built without weights.  Synchronous. */
+gap_status gap_graph_export_weights(const gap_graph *g, int32_t *weights);
+
 /* Vertex count n and stored adjacency entries nnz: 2|E| for an undirected
  * graph, |E| (out-list entries) for a directed one. */
 gap_status gap_graph_info(const gap_graph *g, int64_t *n, int64_t *nnz);
@@ -185,6 +205,35 @@ gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
 gap_status gap_bc(const gap_graph *g, const int32_t *sources,
                   int32_t num_sources, double *scores, uint32_t flags,
                   void *stream);
+
+/*
+ * gap_sssp -- single-source shortest paths (Section 2.1: distances, the
+ * sentinel for unreachable vertices; Section 3: Delta-stepping).
+ *   g       graph from gap_build_csr_weighted (a graph built without weights
+ *           is searched with every weight 1, so the distances are the BFS
+ *           depths); edges are followed along their direction
+ *   source  vertex in [0, n)
+ *   dist    device uint32[n], written: dist[source] = 0, 0xFFFFFFFF for
+ *           unreachable vertices, otherwise the least total weight of a path
+ *   delta   bucket width of Delta-stepping; 0 picks 4 * max weight / mean
+ *           list length, rounded down to a power of two.  Any delta >= 1
+ *           gives the same distances (the answer is unique); delta is the
+ *           one parameter the paper lets depend on the graph (Section 2.3)
+ *   stream  queue for the work; the call only queues it
+ * Scratch (about 16 bytes per vertex plus 1 byte per adjacency entry) comes
+ * from the per-stream pool.
+ * Errors: GAP_EINVAL (NULL argument, source out of range, (n - 1) times
+ * the largest weight not below 2^32 - 1), GAP_ENOMEM, GAP_EDEVICE,
+ * GAP_ETIMEOUT (reported by gap_sssp_ex).
+ */
+gap_status gap_sssp(const gap_graph *g, int32_t source, uint32_t *dist,
+                    uint32_t delta, void *stream);
+
+/* gap_sssp with a statistics output: when phases is not NULL the call
+ * waits for the search and stores the number of relaxation phases run
+ * there, and reports a timed-out device-side wait as GAP_ETIMEOUT. */
+gap_status gap_sssp_ex(const gap_graph *g, int32_t source, uint32_t *dist,
+                       uint32_t delta, void *stream, int32_t *phases);
 
 /* Releases the graph (NULL-safe).  Waits for the device to finish any work
  * queued on it before freeing. */

@@ -366,6 +366,19 @@ gap_status workspace_reserve_bc(Workspace *ws, size_t vertex_bytes, size_t level
   return GAP_OK;
 }
 
+gap_status workspace_reserve_sssp(Workspace *ws, size_t bytes) {
+  if (ws->sp_bytes < bytes) {
+    GAP_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->sp_buf) (void)hipFree(ws->sp_buf);
+    ws->sp_buf = nullptr;
+    ws->sp_bytes = 0;
+    GAP_HIP(hipMalloc(&ws->sp_buf, bytes));
+    ws->sp_bytes = bytes;
+  }
+  if (!ws->sp_host) GAP_HIP(hipHostMalloc(&ws->sp_host, 256));
+  return GAP_OK;
+}
+
 }  // namespace gap
 
 using namespace gap;
@@ -435,8 +448,9 @@ static gap_status require_device() {
   return GAP_OK;
 }
 
-gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges, const int32_t *src,
-                         const int32_t *dst, uint32_t flags, void *stream, gap_graph **out) {
+static gap_status build_checked(int64_t num_vertices, int64_t num_edges, const int32_t *src,
+                                const int32_t *dst, const int32_t *weights, uint32_t flags,
+                                void *stream, gap_graph **out) {
   clear_error();
   if (!out) {
     set_error("gap_build_csr: NULL out");
@@ -457,8 +471,24 @@ gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges, const int32_t 
   }
   gap_status st = require_device();
   if (st != GAP_OK) return st;
-  return build_csr(num_vertices, num_edges, src, dst, (flags & GAP_BUILD_DIRECTED) != 0,
+  return build_csr(num_vertices, num_edges, src, dst, weights, (flags & GAP_BUILD_DIRECTED) != 0,
                    (hipStream_t)stream, out);
+}
+
+gap_status gap_build_csr(int64_t num_vertices, int64_t num_edges, const int32_t *src,
+                         const int32_t *dst, uint32_t flags, void *stream, gap_graph **out) {
+  return build_checked(num_vertices, num_edges, src, dst, nullptr, flags, stream, out);
+}
+
+gap_status gap_build_csr_weighted(int64_t num_vertices, int64_t num_edges, const int32_t *src,
+                                  const int32_t *dst, const int32_t *weights, uint32_t flags,
+                                  void *stream, gap_graph **out) {
+  if (num_edges > 0 && !weights) {
+    clear_error();
+    set_error("gap_build_csr_weighted: NULL weights");
+    return GAP_EINVAL;
+  }
+  return build_checked(num_vertices, num_edges, src, dst, weights, flags, stream, out);
 }
 
 gap_status gap_graph_info(const gap_graph *g, int64_t *n, int64_t *nnz) {
@@ -496,6 +526,22 @@ gap_status gap_graph_export_in(const gap_graph *g, int64_t *row_ptr, int32_t *co
   clear_error();
   return export_csr(g, g ? g->row_ptr_in : nullptr, g ? g->col_in : nullptr, g ? g->nnz_in : 0,
                     row_ptr, col, "gap_graph_export_in");
+}
+
+gap_status gap_graph_export_weights(const gap_graph *g, int32_t *weights) {
+  clear_error();
+  if (!g || !weights) {
+    set_error("gap_graph_export_weights: NULL %s", g ? "weights" : "graph");
+    return GAP_EINVAL;
+  }
+  if (!g->wt) {
+    set_error("gap_graph_export_weights: the graph has no weights");
+    return GAP_EINVAL;
+  }
+  GAP_HIP(hipSetDevice(g->device));
+  if (g->nnz > 0)
+    GAP_HIP(hipMemcpy(weights, g->wt, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost));
+  return GAP_OK;
 }
 
 gap_status gap_graph_directed(const gap_graph *g) {
@@ -586,6 +632,7 @@ void gap_free(gap_graph *g) {
   if (g->col_in && g->col_in != g->col) (void)hipFree(g->col_in);
   if (g->row_ptr) (void)hipFree(g->row_ptr);
   if (g->col) (void)hipFree(g->col);
+  if (g->wt) (void)hipFree(g->wt);
   delete g;
 }
 
@@ -612,6 +659,41 @@ gap_status gap_bc(const gap_graph *g, const int32_t *sources, int32_t num_source
   }
   GAP_HIP(hipSetDevice(g->device));
   return run_bc(g, sources, num_sources, scores, (flags & GAP_BC_RAW) == 0, (hipStream_t)stream);
+}
+
+gap_status gap_sssp_ex(const gap_graph *g, int32_t source, uint32_t *dist, uint32_t delta,
+                       void *stream, int32_t *phases) {
+  clear_error();
+  if (!g || !dist) {
+    set_error("gap_sssp: NULL %s", g ? "dist" : "graph");
+    return GAP_EINVAL;
+  }
+  if (source < 0 || (int64_t)source >= g->n) {
+    set_error("gap_sssp: source %d outside [0, %lld)", source, (long long)g->n);
+    return GAP_EINVAL;
+  }
+  // every distance and the sentinel must fit in 32 bits
+  if ((uint64_t)(g->n - 1) * (uint64_t)g->max_weight >= 0xFFFFFFFFull) {
+    set_error("gap_sssp: (n - 1) * max weight = %llu does not fit below 2^32 - 1",
+              (unsigned long long)((uint64_t)(g->n - 1) * (uint64_t)g->max_weight));
+    return GAP_EINVAL;
+  }
+  if (delta == 0) {
+    // default bucket width: the weight range over the mean list length,
+    // rounded to a power of two (at least 1)
+    const double mean_deg = g->n > 0 ? (double)g->nnz / (double)g->n : 1.0;
+    double d = (double)g->max_weight * 4.0 / std::max(1.0, mean_deg);
+    uint32_t p2 = 1;
+    while (p2 < 0x40000000u && (double)(p2 * 2) <= d) p2 *= 2;
+    delta = p2;
+  }
+  GAP_HIP(hipSetDevice(g->device));
+  return run_sssp(g, source, dist, delta, (hipStream_t)stream, phases);
+}
+
+gap_status gap_sssp(const gap_graph *g, int32_t source, uint32_t *dist, uint32_t delta,
+                    void *stream) {
+  return gap_sssp_ex(g, source, dist, delta, stream, nullptr);
 }
 
 gap_status gap_stream_copy(void *dst, const void *src, int64_t bytes, void *stream) {

@@ -62,6 +62,38 @@ __global__ void k_scatter_cols(const uint64_t *__restrict__ keys, const uint32_t
   }
 }
 
+// Weight of each raw key (mode as in k_make_keys); weights below 1 are
+// reported through *bad (bit 1).
+__global__ void k_make_vals(const int32_t *__restrict__ w, int64_t m, int mode,
+                            int32_t *__restrict__ vals, int *bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+    const int32_t x = w[e];
+    if (x < 1) atomicOr(bad, 2);
+    if (mode == 0) {
+      vals[2 * e] = x;
+      vals[2 * e + 1] = x;
+    } else {
+      vals[e] = x;
+    }
+  }
+}
+
+// The weight of each distinct key: the smallest over its repeats (a run of
+// equal sorted keys).
+__global__ void k_scatter_weights(const uint64_t *__restrict__ keys, const int32_t *__restrict__ vals,
+                                  const uint32_t *__restrict__ flag, const int64_t *__restrict__ pos,
+                                  int64_t len, int32_t *__restrict__ wt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    if (!flag[i]) continue;
+    const uint64_t k = keys[i];
+    int32_t x = vals[i];
+    for (int64_t j = i + 1; j < len && keys[j] == k; ++j) x = min(x, vals[j]);
+    wt[pos[i]] = x;
+  }
+}
+
 // row_ptr from the sorted distinct keys: slot i (0..nnz) owns rows
 // (row(i-1), row(i)], where row(nnz) = n, so empty rows get the next start.
 __global__ void k_row_ptr(const uint64_t *__restrict__ ukeys, int64_t nnz, int64_t n, int bits,
@@ -112,14 +144,16 @@ struct DevBuf {
 
 // One CSR from the raw pairs on the device: keys of the chosen direction(s)
 // (mode as in k_make_keys), sort, drop repeats, scatter columns, offsets.
-// Allocates *row_ptr (int64[n+1]) and *col (int32[nnz]).
-static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, int64_t n, int64_t m,
-                           int bits, int mode, hipStream_t stream, int64_t **row_ptr_out,
-                           int32_t **col_out, int64_t *nnz_out, int64_t *maxdeg_out) {
+// Allocates *row_ptr (int64[n+1]) and *col (int32[nnz]); with d_w (raw
+// weights) also *wt_out (int32[nnz], the smallest weight of each pair).
+static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int32_t *d_w,
+                           int64_t n, int64_t m, int bits, int mode, hipStream_t stream,
+                           int64_t **row_ptr_out, int32_t **col_out, int32_t **wt_out,
+                           int64_t *nnz_out, int64_t *maxdeg_out) {
   const uint64_t mask = (1ull << bits) - 1ull;
   const uint64_t sentinel = (1ull << (2 * bits)) - 1ull;  // = a self-loop key, never kept
   const int64_t len = mode == 0 ? 2 * m : m;
-  DevBuf d_keys, d_sorted, d_flag, d_pos, d_bad, d_tmp, d_maxdeg;
+  DevBuf d_keys, d_sorted, d_flag, d_pos, d_bad, d_tmp, d_maxdeg, d_vals, d_svals;
   GAP_HIP(d_keys.alloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1)));
   GAP_HIP(d_sorted.alloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1)));
   GAP_HIP(d_bad.alloc(sizeof(int)));
@@ -131,21 +165,43 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, int64_t n
     k_make_keys<<<grid_for(m), 256, 0, stream>>>(d_src, d_dst, m, n, bits, sentinel, mode,
                                                  d_keys.as<uint64_t>(), d_bad.as<int>());
     GAP_HIP(hipGetLastError());
+    if (d_w) {
+      GAP_HIP(d_vals.alloc(sizeof(int32_t) * (size_t)len));
+      GAP_HIP(d_svals.alloc(sizeof(int32_t) * (size_t)len));
+      k_make_vals<<<grid_for(m), 256, 0, stream>>>(d_w, m, mode, d_vals.as<int32_t>(),
+                                                   d_bad.as<int>());
+      GAP_HIP(hipGetLastError());
+    }
     int h_bad = 0;
     GAP_HIP(hipMemcpyAsync(&h_bad, d_bad.p, sizeof(int), hipMemcpyDeviceToHost, stream));
     GAP_HIP(hipStreamSynchronize(stream));
     if (h_bad) {
-      set_error("gap_build_csr: an edge endpoint is outside [0, n)");
+      set_error(h_bad & 1 ? "gap_build_csr: an edge endpoint is outside [0, n)"
+                          : "gap_build_csr: a weight is below 1");
       return GAP_EINVAL;
     }
     size_t tmp_bytes = 0;
-    GAP_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, d_keys.as<uint64_t>(),
-                                     d_sorted.as<uint64_t>(), (size_t)len, 0u,
-                                     (unsigned)(2 * bits), stream));
-    GAP_HIP(d_tmp.alloc(tmp_bytes));
-    GAP_HIP(rocprim::radix_sort_keys(d_tmp.p, tmp_bytes, d_keys.as<uint64_t>(),
-                                     d_sorted.as<uint64_t>(), (size_t)len, 0u,
-                                     (unsigned)(2 * bits), stream));
+    if (d_w) {
+      GAP_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, d_keys.as<uint64_t>(),
+                                        d_sorted.as<uint64_t>(), d_vals.as<int32_t>(),
+                                        d_svals.as<int32_t>(), (size_t)len, 0u,
+                                        (unsigned)(2 * bits), stream));
+      GAP_HIP(d_tmp.alloc(tmp_bytes));
+      GAP_HIP(rocprim::radix_sort_pairs(d_tmp.p, tmp_bytes, d_keys.as<uint64_t>(),
+                                        d_sorted.as<uint64_t>(), d_vals.as<int32_t>(),
+                                        d_svals.as<int32_t>(), (size_t)len, 0u,
+                                        (unsigned)(2 * bits), stream));
+      (void)hipFree(d_vals.p);
+      d_vals.p = nullptr;
+    } else {
+      GAP_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, d_keys.as<uint64_t>(),
+                                       d_sorted.as<uint64_t>(), (size_t)len, 0u,
+                                       (unsigned)(2 * bits), stream));
+      GAP_HIP(d_tmp.alloc(tmp_bytes));
+      GAP_HIP(rocprim::radix_sort_keys(d_tmp.p, tmp_bytes, d_keys.as<uint64_t>(),
+                                       d_sorted.as<uint64_t>(), (size_t)len, 0u,
+                                       (unsigned)(2 * bits), stream));
+    }
     (void)hipFree(d_tmp.p);
     d_tmp.p = nullptr;
     GAP_HIP(d_flag.alloc(sizeof(uint32_t) * (size_t)len));
@@ -171,16 +227,23 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, int64_t n
     nnz = last_pos + (int64_t)last_flag;
   }
   int64_t *row_ptr = nullptr;
-  int32_t *col = nullptr;
+  int32_t *col = nullptr, *wt = nullptr;
   hipError_t e1 = hipMalloc(&row_ptr, sizeof(int64_t) * (size_t)(n + 1));
   hipError_t e2 = hipMalloc(&col, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-  if (e1 != hipSuccess || e2 != hipSuccess) {
+  hipError_t e3 = d_w ? hipMalloc(&wt, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)) : hipSuccess;
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
     if (row_ptr) (void)hipFree(row_ptr);
     if (col) (void)hipFree(col);
+    if (wt) (void)hipFree(wt);
     set_error("gap_build_csr: device allocation of the CSR failed");
     return GAP_ENOMEM;
   }
   if (nnz > 0) {
+    if (d_w)
+      k_scatter_weights<<<grid_for(len), 256, 0, stream>>>(d_sorted.as<uint64_t>(),
+                                                           d_svals.as<int32_t>(),
+                                                           d_flag.as<uint32_t>(),
+                                                           d_pos.as<int64_t>(), len, wt);
     // distinct keys go to the (now free) unsorted key buffer
     k_scatter_cols<<<grid_for(len), 256, 0, stream>>>(d_sorted.as<uint64_t>(),
                                                       d_flag.as<uint32_t>(), d_pos.as<int64_t>(),
@@ -196,17 +259,19 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, int64_t n
   if (le != hipSuccess || ce != hipSuccess || se != hipSuccess) {
     (void)hipFree(row_ptr);
     (void)hipFree(col);
+    if (wt) (void)hipFree(wt);
     return hip_fail(le != hipSuccess ? le : (ce != hipSuccess ? ce : se), "gap_build_csr kernels");
   }
   *row_ptr_out = row_ptr;
   *col_out = col;
+  if (wt_out) *wt_out = wt;
   *nnz_out = nnz;
   *maxdeg_out = (int64_t)maxdeg;
   return GAP_OK;
 }
 
-gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, bool directed,
-                     hipStream_t stream, gap_graph **out) {
+gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     const int32_t *weights, bool directed, hipStream_t stream, gap_graph **out) {
   int dev = 0;
   GAP_HIP(hipGetDevice(&dev));
   int bits = 1;
@@ -215,14 +280,18 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
     set_error("gap_build_csr: more than 2^32 directed entries in one call");
     return GAP_EINVAL;
   }
-  DevBuf d_src, d_dst;
+  DevBuf d_src, d_dst, d_w;
   GAP_HIP(d_src.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
   GAP_HIP(d_dst.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
+  if (weights) GAP_HIP(d_w.alloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1)));
   if (m > 0) {
     GAP_HIP(hipMemcpyAsync(d_src.p, src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
                            stream));
     GAP_HIP(hipMemcpyAsync(d_dst.p, dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
                            stream));
+    if (weights)
+      GAP_HIP(hipMemcpyAsync(d_w.p, weights, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
+                             stream));
   }
   gap_graph *g = new (std::nothrow) gap_graph();
   if (!g) {
@@ -231,22 +300,29 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
   }
   g->device = dev;
   g->n = n;
+  g->wt = nullptr;
+  g->max_weight = 1;
+  if (weights)
+    for (int64_t e = 0; e < m; ++e)
+      if (src[e] != dst[e] && weights[e] > g->max_weight) g->max_weight = weights[e];
   g->directed = directed ? 1 : 0;
   // undirected: one symmetric CSR serves both directions; directed: the
   // out-lists (top-down) and the in-lists (bottom-up)
-  gap_status st = csr_pass(d_src.as<int32_t>(), d_dst.as<int32_t>(), n, m, bits, directed ? 1 : 0,
-                           stream, &g->row_ptr, &g->col, &g->nnz, &g->max_degree);
+  gap_status st = csr_pass(d_src.as<int32_t>(), d_dst.as<int32_t>(),
+                           weights ? d_w.as<int32_t>() : nullptr, n, m, bits, directed ? 1 : 0,
+                           stream, &g->row_ptr, &g->col, &g->wt, &g->nnz, &g->max_degree);
   if (st != GAP_OK) {
     delete g;
     return st;
   }
   if (directed) {
     int64_t maxdeg_in = 0;
-    st = csr_pass(d_src.as<int32_t>(), d_dst.as<int32_t>(), n, m, bits, 2, stream,
-                  &g->row_ptr_in, &g->col_in, &g->nnz_in, &maxdeg_in);
+    st = csr_pass(d_src.as<int32_t>(), d_dst.as<int32_t>(), nullptr, n, m, bits, 2, stream,
+                  &g->row_ptr_in, &g->col_in, nullptr, &g->nnz_in, &maxdeg_in);
     if (st != GAP_OK) {
       (void)hipFree(g->row_ptr);
       (void)hipFree(g->col);
+      if (g->wt) (void)hipFree(g->wt);
       delete g;
       return st;
     }

@@ -23,6 +23,8 @@ struct gap_graph {
   int64_t *row_ptr_in;  // device in-lists; the same arrays as row_ptr/col when undirected
   int32_t *col_in;
   int64_t max_degree;
+  int32_t *wt;          // device int32[nnz] out-list weights, or NULL (every weight 1)
+  int32_t max_weight;   // 1 when unweighted
 };
 
 namespace gap {
@@ -93,6 +95,10 @@ struct Workspace {
   void *bc_lv = nullptr;
   void *bc_host = nullptr;  // pinned, 256 bytes
   hipEvent_t bc_event = nullptr;  // marks the depth read-back
+  // shortest paths
+  size_t sp_bytes = 0;
+  void *sp_buf = nullptr;
+  void *sp_host = nullptr;  // pinned, 256 bytes
 };
 
 Workspace *workspace_for(int dev, hipStream_t stream);
@@ -100,6 +106,7 @@ gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const
 gap_status workspace_reserve_recs(Workspace *ws, int32_t nrec);
 gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes);
 gap_status workspace_reserve_bc(Workspace *ws, size_t vertex_bytes, size_t level_bytes);
+gap_status workspace_reserve_sssp(Workspace *ws, size_t bytes);
 
 // Persistent kernels need every workgroup resident at once.  Two of them
 // started on different streams could each get part of the machine and wait
@@ -144,9 +151,12 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
 // Implemented in bc.hip
 gap_status run_bc(const gap_graph *g, const int32_t *sources, int32_t num_sources, double *score,
                   bool normalise, hipStream_t stream);
+// Implemented in sssp.hip
+gap_status run_sssp(const gap_graph *g, int32_t source, uint32_t *dist, uint32_t delta,
+                    hipStream_t stream, int32_t *phases);
 // Implemented in build_csr.hip
-gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, bool directed,
-                     hipStream_t stream, gap_graph **out);
+gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     const int32_t *weights, bool directed, hipStream_t stream, gap_graph **out);
 gap_status stream_copy(void *dst, const void *src, int64_t bytes, hipStream_t stream);
 
 }  // namespace gap

@@ -61,7 +61,8 @@ class DeviceInfo(ctypes.Structure):
 EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_export",
             "gap_graph_export_in", "gap_bfs", "gap_bfs_batch",
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
-            "gap_device_query", "gap_stream_copy", "gap_bc"]
+            "gap_device_query", "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
+            "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex"]
 
 
 def library_path() -> str:
@@ -104,10 +105,16 @@ def load():
         L.gap_device_query.argtypes = [ctypes.POINTER(DeviceInfo)]
         L.gap_stream_copy.argtypes = [vp, vp, i64, vp]
         L.gap_bc.argtypes = [vp, i32p, i32, vp, ctypes.c_uint32, vp]
+        L.gap_build_csr_weighted.argtypes = [i64, i64, i32p, i32p, i32p, ctypes.c_uint32, vp,
+                                             ctypes.POINTER(vp)]
+        L.gap_graph_export_weights.argtypes = [vp, i32p]
+        L.gap_sssp.argtypes = [vp, i32, vp, ctypes.c_uint32, vp]
+        L.gap_sssp_ex.argtypes = [vp, i32, vp, ctypes.c_uint32, vp, i32p]
         for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_graph_export_in",
                      "gap_graph_directed", "gap_bfs", "gap_bfs_ex",
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
-                     "gap_stream_copy", "gap_bc"):
+                     "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
+                     "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
         _apply_tuned(L)
@@ -186,11 +193,13 @@ BUILD_DIRECTED = 1  # gap_build_csr flag
 class Graph:
     """A CSR graph resident in device memory (owns its gap_graph handle)."""
 
-    def __init__(self, handle: int, n: int, nnz: int, directed: bool = False):
+    def __init__(self, handle: int, n: int, nnz: int, directed: bool = False,
+                 weighted: bool = False):
         self.handle = ctypes.c_void_p(handle)
         self.n = n
         self.nnz = nnz
         self.directed = directed
+        self.weighted = weighted
 
     def free(self):
         if self.handle and self.handle.value:
@@ -219,6 +228,12 @@ class Graph:
         """The in-lists (the transpose), as ``export``."""
         return self._export(load().gap_graph_export_in)
 
+    def export_weights(self) -> np.ndarray:
+        """Out-list weights (int32[nnz]) in ``export`` order."""
+        w = np.empty(max(self.nnz, 1), np.int32)
+        _check(load().gap_graph_export_weights(self.handle, _i32p(w)))
+        return w[:self.nnz]
+
     def degrees(self) -> np.ndarray:
         rp, _ = self.export_row_ptr()
         return np.diff(rp)
@@ -227,22 +242,31 @@ class Graph:
         return self._export(load().gap_graph_export, with_col=False)
 
 
-def build_csr(n: int, src: np.ndarray, dst: np.ndarray, stream=None, directed: bool = False) -> Graph:
+def build_csr(n: int, src: np.ndarray, dst: np.ndarray, stream=None, directed: bool = False,
+              weights: Optional[np.ndarray] = None) -> Graph:
     """Build the device CSR from raw pairs (copied).  ``directed`` keeps
-    src[i] -> dst[i] as a one-way edge; otherwise every pair is undirected."""
+    src[i] -> dst[i] as a one-way edge; otherwise every pair is undirected.
+    ``weights`` (int32 per pair, >= 1) are kept for shortest paths."""
     L = load()
     src = np.ascontiguousarray(src, dtype=np.int32)
     dst = np.ascontiguousarray(dst, dtype=np.int32)
     out = ctypes.c_void_p()
-    _check(L.gap_build_csr(int(n), int(src.shape[0]), _i32p(src), _i32p(dst),
-                           BUILD_DIRECTED if directed else 0, _stream_handle(stream),
-                           ctypes.byref(out)))
+    flags = BUILD_DIRECTED if directed else 0
+    if weights is None:
+        _check(L.gap_build_csr(int(n), int(src.shape[0]), _i32p(src), _i32p(dst), flags,
+                               _stream_handle(stream), ctypes.byref(out)))
+    else:
+        w = np.ascontiguousarray(weights, dtype=np.int32)
+        if w.shape[0] != src.shape[0]:
+            raise ValueError("one weight per pair")
+        _check(L.gap_build_csr_weighted(int(n), int(src.shape[0]), _i32p(src), _i32p(dst), _i32p(w),
+                                        flags, _stream_handle(stream), ctypes.byref(out)))
     nn, nnz = ctypes.c_int64(), ctypes.c_int64()
     _check(L.gap_graph_info(out, ctypes.byref(nn), ctypes.byref(nnz)))
     dflag = L.gap_graph_directed(out)
     if dflag < 0:
         _check(dflag)
-    return Graph(out.value, nn.value, nnz.value, directed=bool(dflag))
+    return Graph(out.value, nn.value, nnz.value, directed=bool(dflag), weighted=weights is not None)
 
 
 def graph_info(g: Graph):
@@ -352,6 +376,30 @@ def bc(g: Graph, sources: Sequence[int], scores, normalise: bool = True, stream=
         raise ValueError("scores shorter than n")
     _check(L.gap_bc(g.handle, _i32p(src), int(src.shape[0]), scores.data_ptr(),
                     0 if normalise else BC_RAW, _stream_handle(stream)))
+
+
+SSSP_UNREACHABLE = 0xFFFFFFFF
+
+
+def sssp(g: Graph, source: int, dist, delta: int = 0, stream=None, stats: bool = False):
+    """Shortest-path distances from ``source`` into ``dist`` (a contiguous
+    4-byte-element device tensor of at least n entries, read back as
+    uint32; 0xFFFFFFFF marks unreachable vertices).  With ``stats`` the call
+    waits and returns the number of relaxation phases."""
+    import torch
+    L = load()
+    if dist.element_size() != 4 or not dist.is_cuda or not dist.is_contiguous():
+        raise ValueError("dist must be a contiguous 4-byte device tensor")
+    if dist.numel() < g.n:
+        raise ValueError("dist shorter than n")
+    if stats:
+        ph = ctypes.c_int32(0)
+        _check(L.gap_sssp_ex(g.handle, int(source), dist.data_ptr(), int(delta) & 0xFFFFFFFF,
+                             _stream_handle(stream), ctypes.byref(ph)))
+        return int(ph.value)
+    _check(L.gap_sssp(g.handle, int(source), dist.data_ptr(), int(delta) & 0xFFFFFFFF,
+                      _stream_handle(stream)))
+    return None
 
 
 def device_query() -> dict:
