@@ -13,7 +13,7 @@ undirected edges in the source's connected component.
 Also reported, outside the timed steps: a 64-lane batched search over the
 same sources (per-source throughput vs repeated single-source searches), the
 same R-MAT pairs taken as a directed graph, betweenness centrality from 4
-sources, the serving loop, the measured
+sources, shortest paths with weights 1..255, the serving loop, the measured
 stream-copy bandwidth, the roofline of the dominant kernel and the CPU
 oracle timed on a bounded sample.
 
@@ -325,6 +325,51 @@ def leg_bc(gb, torch, inputs, stream):
     return out
 
 
+def leg_sssp(gb, torch, inputs, stream, sweep=True):
+    """Shortest paths (Delta-stepping) on R-MAT 22 and uniform 2^22 with the
+    generator's weights 1..255: 16 sources each at the default bucket width;
+    m_s as for BFS (undirected edges in the source's component).  With
+    ``sweep``, 4 sources at other widths."""
+    out = {}
+    for name in ("rmat22", "urand22"):
+        el = inputs.workload(name)
+        w = inputs.weights(el, seed=inputs.WEIGHT_SEEDS[name])
+        g = gb.build_csr(el.n, el.src, el.dst, weights=w)
+        srcs = [int(x) for x in inputs.pick_sources(el, 16, seed=inputs.SOURCE_SEEDS[name] + 21)]
+        ce = component_edges(g, el)
+        del el, w
+        dist = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        phases = [gb.sssp(g, s, dist, stats=True) for s in srcs]
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in srcs]
+
+        def timed(delta, ss):
+            best = None
+            for _ in range(2):
+                for i, s in enumerate(ss):
+                    pairs[i][0].record(stream)
+                    gb.sssp(g, s, dist, delta=delta, stream=stream)
+                    pairs[i][1].record(stream)
+                torch.cuda.synchronize()
+                t = np.array([pairs[i][0].elapsed_time(pairs[i][1]) for i in range(len(ss))])
+                best = t if best is None or t.sum() < best.sum() else best
+            return best
+
+        t = timed(0, srcs)
+        ms = np.array([int(ce[s]) for s in srcs], np.int64)
+        out[name] = {"search_ms_median": round(float(np.median(t)), 3),
+                     "gteps_aggregate": round(float(ms.sum() / (t.sum() * 1e-3) / 1e9), 2),
+                     "phases_mean": round(float(np.mean(phases)), 1)}
+        if sweep:
+            out[name]["delta_sweep_ms_median"] = {
+                str(dl): round(float(np.median(timed(dl, srcs[:4]))), 3)
+                for dl in (8, 16, 32, 64, 128, 256, 512)}
+        log(f"sssp {name}: {out[name]}")
+        del dist
+        g.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 MIXED_SCALES = [14, 14, 15, 15, 16, 16, 17, 17, 18, 18, 19, 19, 20, 20, 20, 20]
 
 
@@ -424,9 +469,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", default="rmat22,urand22")
-    ap.add_argument("--legs", default="serving,directed,bc",
+    ap.add_argument("--legs", default="serving,directed,bc,sssp",
                     help="comma list of extra legs reported in detail: serving, directed, bc, "
-                         "grid4096, rmat24, mixed, or all")
+                         "sssp, grid4096, rmat24, mixed, or all")
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--profile-leg", action="store_true",
                     help="for rocprofv3 counter runs: a copy of known size, then one search per "
@@ -599,7 +644,7 @@ def main():
 
     legs = set(args.legs.split(",")) if args.legs else set()
     if "all" in legs:
-        legs = {"serving", "directed", "bc", "grid4096", "rmat24", "mixed"}
+        legs = {"serving", "directed", "bc", "sssp", "grid4096", "rmat24", "mixed"}
     for c in cases:
         c.parent = c.depth = None
     torch.cuda.empty_cache()
@@ -607,6 +652,8 @@ def main():
         detail["rmat22_directed"] = leg_directed(gb, torch, inputs, stream)
     if "bc" in legs:
         detail["bc"] = leg_bc(gb, torch, inputs, stream)
+    if "sssp" in legs:
+        detail["sssp"] = leg_sssp(gb, torch, inputs, stream)
     if "grid4096" in legs:
         detail["grid4096"] = leg_grid(gb, torch, inputs, stream)
     if "rmat24" in legs:

@@ -215,7 +215,7 @@ gap_status gap_bc(const gap_graph *g, const int32_t *sources,
  *   source  vertex in [0, n)
  *   dist    device uint32[n], written: dist[source] = 0, 0xFFFFFFFF for
  *           unreachable vertices, otherwise the least total weight of a path
- *   delta   bucket width of Delta-stepping; 0 picks 4 * max weight / mean
+ *   delta   bucket width of Delta-stepping; 0 picks 16 * max weight / mean
  *           list length, rounded down to a power of two.  Any delta >= 1
  *           gives the same distances (the answer is unique); delta is the
  *           one parameter the paper lets depend on the graph (Section 2.3)

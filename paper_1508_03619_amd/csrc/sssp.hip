@@ -92,6 +92,9 @@ __device__ inline uint32_t items_of(int64_t deg) {
 // Claim of x for the running phase (a near queue) or epoch (a far pile):
 // true for exactly one caller.
 __device__ inline bool claim(uint32_t *stamps, int32_t x, uint32_t stamp) {
+  // a plain read first: most repeat claims in a phase stop here without an
+  // atomic (atomics are carried out at the memory side)
+  if (stamps[x] >= stamp) return false;
   return atomicMax(&stamps[x], stamp) < stamp;
 }
 

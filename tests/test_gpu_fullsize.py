@@ -3,7 +3,8 @@ times: R-MAT scale 22 and uniform-random 2^22 (single-source and the
 64-lane batch), the 4096^2 road-like grid (persistent kernel and captured
 level graphs), R-MAT scale 24 in batches of 64 and 256 lanes, the mixed
 batch of 16 R-MAT graphs of scales 14-20, R-MAT scale 22 taken as a
-directed graph, and betweenness centrality on R-MAT scale 22.
+directed graph, betweenness centrality on R-MAT scale 22, and shortest
+paths on R-MAT and uniform scale 22 with weights 1..255.
 
 Sampled searches are checked in full against the oracle (depths bit-exact,
 parents valid, Section 2.1).  Every lane of a large batch is also checked
@@ -246,3 +247,33 @@ def test_fullsize_bc_rmat22(gpu):
     want = float(np.sum(depth[depth > 0] - 1))
     assert abs(raw.sum() - want) <= 1e-9 * want
     drop(name)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["rmat22", "urand22"])
+def test_fullsize_sssp(gpu, name):
+    """Shortest paths at scale 22 with the generator's weights 1..255:
+    two sources against Dijkstra (exact distances), with the default bucket
+    width the benchmark uses and one other."""
+    import torch
+    from paper_1508_03619_amd import inputs, gapbfs as gb
+    el = inputs.workload(name)
+    w = inputs.weights(el, seed=inputs.WEIGHT_SEEDS[name])
+    say(f"{name}: weighted device CSR")
+    g = gb.build_csr(el.n, el.src, el.dst, weights=w)
+    say(f"{name}: oracle weighted adjacency")
+    A = oracle.WeightedAdjacency(el.n, el.src, el.dst, w)
+    srcs = [int(x) for x in inputs.pick_sources(el, 2, seed=inputs.SOURCE_SEEDS[name] + 21)]
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for s in srcs:
+        say(f"{name}: Dijkstra from {s}")
+        ref = A.sssp(s)
+        ref = np.where(ref < 0, 0xFFFFFFFF, ref)
+        for delta in (0, 256):
+            say(f"{name}: gpu delta={delta}")
+            gb.sssp(g, s, out, delta=delta)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy().view(np.uint32).astype(np.int64)
+            bad = np.nonzero(got != ref)[0]
+            assert bad.size == 0, (name, s, delta, bad.size, int(bad[0]), got[bad[0]], ref[bad[0]])
+    g.free()
