@@ -24,6 +24,10 @@ Definitions followed (the paper, arXiv 1508.03619):
   * Shortest paths (Section 2.1): dist[source] = 0, unreachable vertices
     get the sentinel (-1 here), otherwise the least total weight of a path;
     Dijkstra's algorithm, the paper's verifier for this kernel (Section 3).
+  * Connected components (Section 2.1): ``components`` labels every vertex
+    with the smallest vertex of its (weak) component by union-find over the
+    raw pairs; ``Adjacency.cc_check`` is the paper's verifier (Section 3)
+    for any labelling.
 
 The C implementation is ``oracle.c``; ``build()`` compiles it with gcc.
 """
@@ -85,6 +89,8 @@ def _bind(path: str):
     lib.oracle_build_weighted_adjacency.restype = ctypes.c_int64
     lib.oracle_sssp.argtypes = [ctypes.c_int64, i64p, i32p, i32p, ctypes.c_int32, i64p]
     lib.oracle_sssp.restype = ctypes.c_int64
+    lib.oracle_cc_check.argtypes = [ctypes.c_int64, i64p, i32p, i32p, i64p]
+    lib.oracle_cc_check.restype = ctypes.c_int
     return lib
 
 
@@ -167,6 +173,15 @@ class Adjacency:
             raise ValueError("oracle_bc: bad input")
         return out
 
+    def cc_check(self, label) -> tuple:
+        """(code, bad_vertex) of the paper's component verifier; code 0 means
+        the labelling is valid (this adjacency must be the undirected one)."""
+        bad = ctypes.c_int64(-1)
+        lab = np.ascontiguousarray(label, dtype=np.int32)
+        code = self._lib.oracle_cc_check(self.n, _i64(self.offsets), _i32(self.adj), _i32(lab),
+                                         ctypes.byref(bad))
+        return int(code), int(bad.value)
+
     def component_edges(self, depth: np.ndarray) -> int:
         """Undirected edges inside the reached set: half the degree sum."""
         deg = self.degree()
@@ -208,7 +223,8 @@ class WeightedAdjacency:
 
 
 def components(n: int, src: np.ndarray, dst: np.ndarray, _lib=None) -> np.ndarray:
-    """Union-find component representative for every vertex (raw edges)."""
+    """Union-find component representative for every vertex (raw edges,
+    taken as undirected): the smallest vertex of its component."""
     L = _lib or lib()
     src = np.ascontiguousarray(src, dtype=np.int32)
     dst = np.ascontiguousarray(dst, dtype=np.int32)

@@ -1,6 +1,7 @@
 /*
- * CPU ORACLE FOR BREADTH-FIRST SEARCH, BETWEENNESS CENTRALITY AND
- * SINGLE-SOURCE SHORTEST PATHS -- TEST INFRASTRUCTURE ONLY.
+ * CPU ORACLE FOR BREADTH-FIRST SEARCH, BETWEENNESS CENTRALITY,
+ * SINGLE-SOURCE SHORTEST PATHS AND CONNECTED COMPONENTS -- TEST
+ * INFRASTRUCTURE ONLY.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * use this file.  It shares no code with the GPU library: it builds its own
@@ -25,6 +26,10 @@
  * Shortest paths (Section 2.1): distances by Dijkstra's algorithm (the
  * paper's verifier for this kernel, Section 3) over a weighted adjacency
  * in which a repeated pair keeps its smallest weight; see oracle_sssp.
+ * Connected components (Section 2.1): union-find over the raw pairs taken
+ * as undirected (weak components of a directed graph), each vertex
+ * labelled with the smallest vertex of its component (oracle_components),
+ * and the paper's verifier for any labelling (oracle_cc_check).
  *
  * Pins (tests): exhaustive small graphs against Floyd-Warshall and boolean
  * matrix powers, random graphs against scipy's csgraph, closed forms (path,
@@ -510,4 +515,69 @@ int64_t oracle_sssp(int64_t n, const int64_t *offsets, const int32_t *adj,
   free(h);
   free(done);
   return reached;
+}
+
+/* ---- connected components check (Section 3, CC verifier) ---------------- */
+
+/*
+ * Checks a component labelling against the equivalence of Section 2.1
+ * (same label if and only if an undirected path joins the vertices) the way
+ * the paper's verifier does: one traversal per label over the undirected
+ * adjacency (offsets, adj), which must meet no other label, and no label
+ * may start a second traversal.  Returns 0 if the labelling is valid, 1 if
+ * a traversal met another label (*bad = that vertex), 2 if two components
+ * share a label (*bad = first vertex of the second one), -1 on bad input.
+ */
+int oracle_cc_check(int64_t n, const int64_t *offsets, const int32_t *adj,
+                    const int32_t *label, int64_t *bad) {
+  if (n <= 0 || !offsets || !label) return -1;
+  if (bad) *bad = -1;
+  char *seen = (char *)calloc((size_t)n, 1);
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  /* labels are arbitrary int32 values: remember used ones in a hash set */
+  int64_t cap = 1;
+  while (cap < 2 * n) cap <<= 1;
+  int64_t *used = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+  if (!seen || !queue || !used) {
+    free(seen);
+    free(queue);
+    free(used);
+    return -1;
+  }
+  for (int64_t i = 0; i < cap; ++i) used[i] = INT64_MIN;
+  int rc = 0;
+  for (int64_t s = 0; s < n && rc == 0; ++s) {
+    if (seen[s]) continue;
+    const int32_t L = label[s];
+    uint64_t h = ((uint64_t)(uint32_t)L * 0x9E3779B97F4A7C15ULL) & (uint64_t)(cap - 1);
+    while (used[h] != INT64_MIN && used[h] != (int64_t)L) h = (h + 1) & (uint64_t)(cap - 1);
+    if (used[h] == (int64_t)L) {
+      rc = 2;
+      if (bad) *bad = s;
+      break;
+    }
+    used[h] = (int64_t)L;
+    int64_t head = 0, tail = 0;
+    queue[tail++] = (int32_t)s;
+    seen[s] = 1;
+    while (head < tail && rc == 0) {
+      const int32_t u = queue[head++];
+      for (int64_t i = offsets[u]; i < offsets[u + 1]; ++i) {
+        const int32_t v = adj[i];
+        if (label[v] != L) {
+          rc = 1;
+          if (bad) *bad = v;
+          break;
+        }
+        if (!seen[v]) {
+          seen[v] = 1;
+          queue[tail++] = v;
+        }
+      }
+    }
+  }
+  free(seen);
+  free(queue);
+  free(used);
+  return rc;
 }

@@ -141,3 +141,20 @@ def test_sssp_mutant_is_caught(tmp_path, name):
     from tests import test_oracle_sssp as TS
     L = _compile_mutant(tmp_path, SSSP_MUTANTS[name])
     assert not TS.sssp_pins_ok(L), f"mutant {name} passed every shortest-path pin"
+
+
+# Mistakes in union-find and the component verifier, caught by the CC pins.
+CC_MUTANTS = {
+    "cc_larger_root_wins": [("      if (ra < rb)\n        label[rb] = ra;\n      else\n        label[ra] = rb;",
+                             "      if (ra > rb)\n        label[rb] = ra;\n      else\n        label[ra] = rb;")],
+    "cc_skips_last_edge": [("  for (int64_t e = 0; e < m; ++e) {\n    int32_t a = src[e], b = dst[e];\n    if (a < 0",
+                            "  for (int64_t e = 0; e + 1 < m; ++e) {\n    int32_t a = src[e], b = dst[e];\n    if (a < 0")],
+    "cc_check_ignores_reuse": [("    if (used[h] == (int64_t)L) {\n      rc = 2;", "    if (0) {\n      rc = 2;")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(CC_MUTANTS))
+def test_cc_mutant_is_caught(tmp_path, name):
+    from tests import test_oracle_cc as TC
+    L = _compile_mutant(tmp_path, CC_MUTANTS[name])
+    assert not TC.cc_pins_ok(L), f"mutant {name} passed every component pin"
