@@ -13,7 +13,8 @@ undirected edges in the source's connected component.
 Also reported, outside the timed steps: a 64-lane batched search over the
 same sources (per-source throughput vs repeated single-source searches), the
 same R-MAT pairs taken as a directed graph, betweenness centrality from 4
-sources, shortest paths with weights 1..255, the serving loop, the measured
+sources, shortest paths with weights 1..255, connected components, the
+serving loop, the measured
 stream-copy bandwidth, the roofline of the dominant kernel and the CPU
 oracle timed on a bounded sample.
 
@@ -370,6 +371,29 @@ def leg_sssp(gb, torch, inputs, stream, sweep=True):
     return out
 
 
+def leg_cc(gb, torch, inputs, stream):
+    """Connected components on R-MAT 22, uniform 2^22 and the directed
+    R-MAT 22 (weak components): best of 5 runs; GTEPS = stored adjacency
+    entries / 2 (undirected) or entries (directed) per second."""
+    out = {}
+    for name in ("rmat22", "urand22", "rmat22d"):
+        el = inputs.workload(name)
+        directed = name in inputs.DIRECTED
+        g = gb.build_csr(el.n, el.src, el.dst, directed=directed)
+        del el
+        lab = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        t = time_launches(torch, stream, lambda: gb.cc(g, lab, stream=stream), reps=5)
+        edges = g.nnz if directed else g.nnz // 2
+        ncomp = int(torch.unique(lab).numel())
+        out[name] = {"ms": round(t, 3), "gteps": round(edges / (t * 1e-3) / 1e9, 2),
+                     "components": ncomp}
+        log(f"cc {name}: {out[name]}")
+        del lab
+        g.free()
+        torch.cuda.empty_cache()
+    return out
+
+
 MIXED_SCALES = [14, 14, 15, 15, 16, 16, 17, 17, 18, 18, 19, 19, 20, 20, 20, 20]
 
 
@@ -469,9 +493,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", default="rmat22,urand22")
-    ap.add_argument("--legs", default="serving,directed,bc,sssp",
+    ap.add_argument("--legs", default="serving,directed,bc,sssp,cc",
                     help="comma list of extra legs reported in detail: serving, directed, bc, "
-                         "sssp, grid4096, rmat24, mixed, or all")
+                         "sssp, cc, grid4096, rmat24, mixed, or all")
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--profile-leg", action="store_true",
                     help="for rocprofv3 counter runs: a copy of known size, then one search per "
@@ -644,7 +668,7 @@ def main():
 
     legs = set(args.legs.split(",")) if args.legs else set()
     if "all" in legs:
-        legs = {"serving", "directed", "bc", "sssp", "grid4096", "rmat24", "mixed"}
+        legs = {"serving", "directed", "bc", "sssp", "cc", "grid4096", "rmat24", "mixed"}
     for c in cases:
         c.parent = c.depth = None
     torch.cuda.empty_cache()
@@ -654,6 +678,8 @@ def main():
         detail["bc"] = leg_bc(gb, torch, inputs, stream)
     if "sssp" in legs:
         detail["sssp"] = leg_sssp(gb, torch, inputs, stream)
+    if "cc" in legs:
+        detail["cc"] = leg_cc(gb, torch, inputs, stream)
     if "grid4096" in legs:
         detail["grid4096"] = leg_grid(gb, torch, inputs, stream)
     if "rmat24" in legs:

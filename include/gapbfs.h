@@ -235,6 +235,19 @@ gap_status gap_sssp(const gap_graph *g, int32_t source, uint32_t *dist,
 gap_status gap_sssp_ex(const gap_graph *g, int32_t source, uint32_t *dist,
                        uint32_t delta, void *stream, int32_t *phases);
 
+/*
+ * gap_cc -- connected components (Section 2.1: two vertices share a label
+ * if and only if an undirected path joins them; for a directed graph the
+ * weak components; a vertex without edges is alone).
+ *   g       graph from gap_build_csr or gap_build_csr_weighted
+ *   labels  device int32[n], written: the smallest vertex of each vertex's
+ *           component (so the labelling is unique)
+ *   stream  queue for the work; the call only queues it
+ * Scratch (8 bytes per 32 adjacency entries) comes from the per-stream
+ * pool.  Errors: GAP_EINVAL (NULL argument), GAP_ENOMEM, GAP_EDEVICE.
+ */
+gap_status gap_cc(const gap_graph *g, int32_t *labels, void *stream);
+
 /* Releases the graph (NULL-safe).  Waits for the device to finish any work
  * queued on it before freeing. */
 void gap_free(gap_graph *g);

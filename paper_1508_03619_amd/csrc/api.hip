@@ -379,6 +379,18 @@ gap_status workspace_reserve_sssp(Workspace *ws, size_t bytes) {
   return GAP_OK;
 }
 
+gap_status workspace_reserve_cc(Workspace *ws, size_t bytes) {
+  if (ws->cc_bytes < bytes) {
+    GAP_HIP(hipStreamSynchronize(ws->stream));
+    if (ws->cc_buf) (void)hipFree(ws->cc_buf);
+    ws->cc_buf = nullptr;
+    ws->cc_bytes = 0;
+    GAP_HIP(hipMalloc(&ws->cc_buf, bytes));
+    ws->cc_bytes = bytes;
+  }
+  return GAP_OK;
+}
+
 }  // namespace gap
 
 using namespace gap;
@@ -695,6 +707,16 @@ gap_status gap_sssp_ex(const gap_graph *g, int32_t source, uint32_t *dist, uint3
 gap_status gap_sssp(const gap_graph *g, int32_t source, uint32_t *dist, uint32_t delta,
                     void *stream) {
   return gap_sssp_ex(g, source, dist, delta, stream, nullptr);
+}
+
+gap_status gap_cc(const gap_graph *g, int32_t *labels, void *stream) {
+  clear_error();
+  if (!g || !labels) {
+    set_error("gap_cc: NULL %s", g ? "labels" : "graph");
+    return GAP_EINVAL;
+  }
+  GAP_HIP(hipSetDevice(g->device));
+  return run_cc(g, labels, (hipStream_t)stream);
 }
 
 gap_status gap_stream_copy(void *dst, const void *src, int64_t bytes, void *stream) {

@@ -99,6 +99,9 @@ struct Workspace {
   size_t sp_bytes = 0;
   void *sp_buf = nullptr;
   void *sp_host = nullptr;  // pinned, 256 bytes
+  // connected components
+  size_t cc_bytes = 0;
+  void *cc_buf = nullptr;
 };
 
 Workspace *workspace_for(int dev, hipStream_t stream);
@@ -107,6 +110,7 @@ gap_status workspace_reserve_recs(Workspace *ws, int32_t nrec);
 gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes);
 gap_status workspace_reserve_bc(Workspace *ws, size_t vertex_bytes, size_t level_bytes);
 gap_status workspace_reserve_sssp(Workspace *ws, size_t bytes);
+gap_status workspace_reserve_cc(Workspace *ws, size_t bytes);
 
 // Persistent kernels need every workgroup resident at once.  Two of them
 // started on different streams could each get part of the machine and wait
@@ -151,6 +155,8 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
 // Implemented in bc.hip
 gap_status run_bc(const gap_graph *g, const int32_t *sources, int32_t num_sources, double *score,
                   bool normalise, hipStream_t stream);
+// Implemented in cc.hip
+gap_status run_cc(const gap_graph *g, int32_t *labels, hipStream_t stream);
 // Implemented in sssp.hip
 gap_status run_sssp(const gap_graph *g, int32_t source, uint32_t *dist, uint32_t delta,
                     hipStream_t stream, int32_t *phases);

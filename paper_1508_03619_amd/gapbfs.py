@@ -62,7 +62,7 @@ EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_
             "gap_graph_export_in", "gap_bfs", "gap_bfs_batch",
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
             "gap_device_query", "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
-            "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex"]
+            "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc"]
 
 
 def library_path() -> str:
@@ -110,11 +110,12 @@ def load():
         L.gap_graph_export_weights.argtypes = [vp, i32p]
         L.gap_sssp.argtypes = [vp, i32, vp, ctypes.c_uint32, vp]
         L.gap_sssp_ex.argtypes = [vp, i32, vp, ctypes.c_uint32, vp, i32p]
+        L.gap_cc.argtypes = [vp, vp, vp]
         for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_graph_export_in",
                      "gap_graph_directed", "gap_bfs", "gap_bfs_ex",
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
                      "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
-                     "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex"):
+                     "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
         _apply_tuned(L)
@@ -400,6 +401,15 @@ def sssp(g: Graph, source: int, dist, delta: int = 0, stream=None, stats: bool =
     _check(L.gap_sssp(g.handle, int(source), dist.data_ptr(), int(delta) & 0xFFFFFFFF,
                       _stream_handle(stream)))
     return None
+
+
+def cc(g: Graph, labels, stream=None):
+    """Connected-component labels (the smallest vertex of each component)
+    into ``labels``, a contiguous int32 device tensor of at least n entries."""
+    L = load()
+    if labels.numel() < g.n:
+        raise ValueError("labels shorter than n")
+    _check(L.gap_cc(g.handle, _ptr(labels), _stream_handle(stream)))
 
 
 def device_query() -> dict:

@@ -63,6 +63,7 @@ def test_argument_errors_without_device(lib):
     assert lib.gap_bfs_batch(None, 1, None, None, 1, None, None, None) == gapbfs.GAP_EINVAL
     assert lib.gap_bc(None, None, 4, None, 0, None) == gapbfs.GAP_EINVAL
     assert lib.gap_sssp(None, 0, None, 0, None) == gapbfs.GAP_EINVAL
+    assert lib.gap_cc(None, None, None) == gapbfs.GAP_EINVAL
     assert lib.gap_graph_export_weights(None, None) == gapbfs.GAP_EINVAL
     s1 = (ctypes.c_int32 * 1)(0)
     assert lib.gap_build_csr_weighted(4, 1, s1, s1, None, 0, None, ctypes.byref(out)) == gapbfs.GAP_EINVAL

@@ -3,8 +3,9 @@ times: R-MAT scale 22 and uniform-random 2^22 (single-source and the
 64-lane batch), the 4096^2 road-like grid (persistent kernel and captured
 level graphs), R-MAT scale 24 in batches of 64 and 256 lanes, the mixed
 batch of 16 R-MAT graphs of scales 14-20, R-MAT scale 22 taken as a
-directed graph, betweenness centrality on R-MAT scale 22, and shortest
-paths on R-MAT and uniform scale 22 with weights 1..255.
+directed graph, betweenness centrality on R-MAT scale 22, shortest paths
+on R-MAT and uniform scale 22 with weights 1..255, and connected components
+at scale 22.
 
 Sampled searches are checked in full against the oracle (depths bit-exact,
 parents valid, Section 2.1).  Every lane of a large batch is also checked
@@ -276,4 +277,24 @@ def test_fullsize_sssp(gpu, name):
             got = out.cpu().numpy().view(np.uint32).astype(np.int64)
             bad = np.nonzero(got != ref)[0]
             assert bad.size == 0, (name, s, delta, bad.size, int(bad[0]), got[bad[0]], ref[bad[0]])
+    g.free()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["rmat22", "urand22", "rmat22d"])
+def test_fullsize_cc(gpu, name):
+    """Connected components at scale 22 (weak components for the directed
+    R-MAT): every label against the oracle's union-find."""
+    import torch
+    from paper_1508_03619_amd import inputs, gapbfs as gb
+    el = inputs.workload(name)
+    g = gb.build_csr(el.n, el.src, el.dst, directed=name.endswith("d"))
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    say(f"{name}: components")
+    gb.cc(g, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle.components(el.n, el.src, el.dst)
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, (name, bad.size, int(bad[0]), got[bad[0]], ref[bad[0]])
     g.free()
