@@ -32,7 +32,7 @@ def kernel_source_hash() -> str:
 
 
 def short(name: str) -> str:
-    return name.split("(")[0].replace("void ", "")
+    return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
 
 
 def stats(args):
