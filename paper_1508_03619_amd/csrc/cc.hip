@@ -15,10 +15,20 @@
 // value still names an ancestor, and a hook on a vertex that stopped being
 // a root fails its compare-and-swap and retries from the fresh value.
 //
+// Most edges need no hook: they join vertices already in one tree.  So the
+// edges are taken in two steps (the sampling scheme of GPU union-find
+// codes): first every vertex is hooked to its first kSampleRounds list
+// entries and the forest is flattened; the most frequent root among
+// kSample spread-out vertices names the giant tree; then only vertices
+// outside it walk their lists (all entries, and for a directed graph its
+// in-list too, so an edge from the giant tree into a small one is seen
+// from the small end).  Skipping the giant tree's vertices is safe for any
+// choice of it: an edge to a vertex outside it is hooked from that end.
 // Lists of up to kLight entries are walked by one lane each; longer lists
-// become chunk items of kChunk entries walked by a whole wave.  An
-// undirected graph hooks each edge once (from its larger end); a directed
-// graph hooks every out-list entry.
+// become chunk items of kChunk entries walked by a whole wave.
+
+#include <algorithm>
+#include <vector>
 
 #include "runtime.h"
 
@@ -28,6 +38,8 @@ namespace {
 constexpr int kCcBlock = 256;
 constexpr int kLight = 32;
 constexpr int kChunk = 256;
+constexpr int kSampleRounds = 2;
+constexpr int kSample = 1024;
 
 __global__ __launch_bounds__(kCcBlock) void k_cc_init(int64_t n, int32_t *__restrict__ parent) {
   for (int64_t v = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; v < n;
@@ -69,16 +81,28 @@ struct CcArgs {
   int32_t *parent;
   int2 *items;
   unsigned int *nitems;
-  int directed;
+  int32_t skip;  // vertices whose root is this one do not walk their lists
 };
 
-// Short lists, one lane each; long lists become chunk items.
+// Vertex u hooked to its first kSampleRounds list entries.
+__global__ __launch_bounds__(kCcBlock) void k_cc_sample(int64_t n, const int64_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col,
+                                                        int32_t *parent) {
+  for (int64_t u = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * kCcBlock) {
+    const int64_t beg = rp[u], deg = rp[u + 1] - beg;
+    for (int r = 0; r < kSampleRounds && r < deg; ++r) hook(parent, (int32_t)u, col[beg + r]);
+  }
+}
+
+// Short lists of vertices outside the giant tree, one lane each; long
+// lists become chunk items.
 __global__ __launch_bounds__(kCcBlock) void k_cc_light(CcArgs a) {
   const int64_t stride = (int64_t)gridDim.x * kCcBlock;
   const int64_t n_round = (a.n + stride - 1) / stride * stride;  // whole waves iterate together
   for (int64_t u = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; u < n_round; u += stride) {
     int64_t beg = 0, deg = 0;
-    if (u < a.n) {
+    if (u < a.n && find_root(a.parent, (int32_t)u) != a.skip) {
       beg = a.rp[u];
       deg = a.rp[u + 1] - beg;
     }
@@ -91,12 +115,8 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_light(CcArgs a) {
       base = __shfl(base, 0, kWave);
       for (uint32_t k = 0; k < nch; ++k) a.items[base + off + k] = make_int2((int)u, (int)k);
     }
-    if (nch == 0) {
-      for (int64_t e = beg; e < beg + deg; ++e) {
-        const int32_t v = a.col[e];
-        if (v < u || (a.directed && v != u)) hook(a.parent, (int32_t)u, v);
-      }
-    }
+    if (nch == 0)
+      for (int64_t e = beg; e < beg + deg; ++e) hook(a.parent, (int32_t)u, a.col[e]);
   }
 }
 
@@ -110,10 +130,15 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_heavy(CcArgs a) {
     const int32_t u = it.x;
     const int64_t beg = a.rp[u] + (int64_t)it.y * kChunk;
     const int64_t end = min(beg + (int64_t)kChunk, a.rp[u + 1]);
-    for (int64_t e = beg + lane; e < end; e += kWave) {
-      const int32_t v = a.col[e];
-      if (v < u || (a.directed && v != u)) hook(a.parent, u, v);
-    }
+    for (int64_t e = beg + lane; e < end; e += kWave) hook(a.parent, u, a.col[e]);
+  }
+}
+
+// The roots of kSample vertices spread over the vertex range.
+__global__ void k_cc_pick(int64_t n, const int32_t *__restrict__ parent, int32_t *out) {
+  for (int i = threadIdx.x; i < kSample; i += blockDim.x) {
+    const int64_t v = (int64_t)(((uint64_t)i * 2654435761ull + 12345ull) % (uint64_t)n);
+    out[i] = parent[v];
   }
 }
 
@@ -151,25 +176,55 @@ gap_status run_cc(const gap_graph *g, int32_t *labels, hipStream_t stream) {
     set_error("gap_cc: no workspace for the stream");
     return GAP_ENOMEM;
   }
-  // chunk items: sum over long lists of ceil(deg / kChunk)
+  // chunk items: sum over long lists of ceil(deg / kChunk), per list set
   const int64_t cap_items = g->nnz / kChunk + g->nnz / (kLight + 1) + 1;
-  st = workspace_reserve_cc(ws, sizeof(int2) * (size_t)cap_items + 512);
+  st = workspace_reserve_cc(ws, sizeof(int2) * (size_t)cap_items + sizeof(int32_t) * kSample + 1024);
   if (st != GAP_OK) return st;
   char *p = reinterpret_cast<char *>(ws->cc_buf);
-  CcArgs a{};
-  a.n = g->n;
-  a.rp = g->row_ptr;
-  a.col = g->col;
-  a.parent = labels;
-  a.nitems = carve<unsigned int>(p, 1);
-  a.items = carve<int2>(p, cap_items);
-  a.directed = g->directed;
+  unsigned int *nitems = carve<unsigned int>(p, 1);
+  int32_t *picks = carve<int32_t>(p, kSample);
+  int2 *items = carve<int2>(p, cap_items);
   const int grid = di->cus * 8;
-  GAP_HIP(hipMemsetAsync(a.nitems, 0, sizeof(unsigned int), stream));
-  k_cc_init<<<grid, kCcBlock, 0, stream>>>(g->n, labels);
-  k_cc_light<<<grid, kCcBlock, 0, stream>>>(a);
-  k_cc_heavy<<<grid, kCcBlock, 0, stream>>>(a);
-  k_cc_compress<<<grid, kCcBlock, 0, stream>>>(g->n, labels);
+  const int64_t n = g->n;
+  k_cc_init<<<grid, kCcBlock, 0, stream>>>(n, labels);
+  k_cc_sample<<<grid, kCcBlock, 0, stream>>>(n, g->row_ptr, g->col, labels);
+  k_cc_compress<<<grid, kCcBlock, 0, stream>>>(n, labels);
+  k_cc_pick<<<1, 256, 0, stream>>>(n, labels, picks);
+  GAP_HIP(hipGetLastError());
+  int32_t *h = reinterpret_cast<int32_t *>(ws->cc_host);
+  GAP_HIP(hipMemcpyAsync(h, picks, sizeof(int32_t) * kSample, hipMemcpyDeviceToHost, stream));
+  GAP_HIP(hipStreamSynchronize(stream));
+  // the most frequent root among the picks
+  std::vector<int32_t> v(h, h + kSample);
+  std::sort(v.begin(), v.end());
+  int32_t giant = v[0];
+  int best = 0;
+  for (size_t i = 0; i < v.size();) {
+    size_t j = i;
+    while (j < v.size() && v[j] == v[i]) ++j;
+    if ((int)(j - i) > best) {
+      best = (int)(j - i);
+      giant = v[i];
+    }
+    i = j;
+  }
+  // the lists of the vertices outside the giant tree: out-lists, and the
+  // in-lists of a directed graph
+  const int passes = g->directed ? 2 : 1;
+  for (int pass = 0; pass < passes; ++pass) {
+    CcArgs a{};
+    a.n = n;
+    a.rp = pass == 0 ? g->row_ptr : g->row_ptr_in;
+    a.col = pass == 0 ? g->col : g->col_in;
+    a.parent = labels;
+    a.items = items;
+    a.nitems = nitems;
+    a.skip = giant;
+    GAP_HIP(hipMemsetAsync(nitems, 0, sizeof(unsigned int), stream));
+    k_cc_light<<<grid, kCcBlock, 0, stream>>>(a);
+    k_cc_heavy<<<grid, kCcBlock, 0, stream>>>(a);
+  }
+  k_cc_compress<<<grid, kCcBlock, 0, stream>>>(n, labels);
   GAP_HIP(hipGetLastError());
   return GAP_OK;
 }
