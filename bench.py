@@ -97,7 +97,7 @@ def committed_traffic(kernel):
     from paper_1508_03619_amd.rocprof_summary import kernel_source_hash
     try:
         tj = json.load(open(tpath))
-        if tj.get("source_hash") == kernel_source_hash():
+        if tj.get("source_hash") == kernel_source_hash(kernel):
             return int(tj.get("bytes_per_launch"))
     except (OSError, ValueError, TypeError):
         pass

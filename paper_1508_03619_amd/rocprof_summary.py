@@ -22,13 +22,26 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def kernel_source_hash() -> str:
+# Files that hold each profiled kernel's device code and its launch; a
+# summary stays valid while these are unchanged.  Other kernels: every file.
+KERNEL_SOURCES = {
+    "k_bfs_persistent": ["bfs.hip", "bfs_kernels.h", "common.h"],
+    "k_msbfs": ["msbfs.hip", "bfs_kernels.h", "common.h"],
+}
+
+
+def kernel_source_hash(kernel: str | None = None) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    for f in sorted(os.listdir(csrc)):
+    files = KERNEL_SOURCES.get(kernel) if kernel else None
+    for f in sorted(files or os.listdir(csrc)):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
+
+
+def hash_line(kernels) -> str:
+    return "# kernel-source hashes: " + ", ".join(f"{k}={kernel_source_hash(k)}" for k in kernels)
 
 
 def short(name: str) -> str:
@@ -39,7 +52,7 @@ def stats(args):
     rows = list(csv.DictReader(open(args.csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = [f"# rocprofv3 kernel statistics", f"# command: {args.cmd}",
-             f"# kernel-source hash: {kernel_source_hash()}", "",
+             hash_line(args.kernel or ["k_bfs_persistent", "k_msbfs"]) + f", all sources={kernel_source_hash()}", "",
              f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total%':>7s}"]
     for r in rows[:25]:
         lines.append(f"{short(r['Name'])[:60]:60s} {int(r['Calls']):7d} {float(r['AverageNs'])/1e3:10.2f} "
@@ -84,7 +97,7 @@ def traffic(args):
     res = {
         "kernel": args.kernel,
         "command": args.cmd,
-        "source_hash": kernel_source_hash(),
+        "source_hash": kernel_source_hash(args.kernel),
         "dispatches": {"fetch": nf, "write": nw},
         "raw_fetch_per_launch": kf, "raw_write_per_launch": kw,
         "copy_bytes": args.copy_bytes,
@@ -109,7 +122,7 @@ def counters(args):
             for k, vals in _counter_per_dispatch(path, c).items():
                 per.setdefault(k, {})[c] = vals
     lines = ["# rocprofv3 counters, average per dispatch", f"# command: {args.cmd}",
-             f"# kernel-source hash: {kernel_source_hash()}", ""]
+             hash_line([k for k in args.kernel if k in KERNEL_SOURCES]), ""]
     for want in args.kernel:
         ks = [k for k in per if want in k]
         for k in ks:
@@ -134,6 +147,7 @@ def main():
     s.add_argument("csv")
     s.add_argument("out")
     s.add_argument("--cmd", default="")
+    s.add_argument("--kernel", action="append", default=[])
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
