@@ -291,7 +291,7 @@ typedef struct gap_params {
                             queued on different streams can overlap) */
   int32_t small_frontier; /* persistent single-source schedule: a top-down
                             level whose frontier and frontier edges are both
-                            at most this runs on 16 workgroups while the
+                            at most this runs on 32 workgroups while the
                             rest wait (0 = every level on the whole grid) */
   int32_t lds_bitmap;    /* persistent single-source schedule: 1 = bottom-up
                             steps copy the frontier bitmap (n/8 bytes) into

@@ -69,6 +69,7 @@ struct CoopState {
   std::mutex mu;
   std::vector<hipEvent_t> ev;      // ring of k events
   std::vector<bool> recorded;
+  std::vector<hipStream_t> on;     // stream of the launch each event follows
   int k = 0;
   unsigned long long next = 0;     // launches ordered so far
 };
@@ -85,19 +86,23 @@ gap_status coop_begin(int dev, hipStream_t s, int k, CoopOrder *o) {
   CoopState *cs = coop_state(dev);
   o->lock = std::unique_lock<std::mutex>(cs->mu);
   if (k < 1) k = 1;
+  // a launch queued earlier on the same stream is ordered by the stream
+  // itself: no wait is queued for it
   if (cs->k != k) {
     // a new ring size: the first launch waits for every launch of the old ring
     for (size_t i = 0; i < cs->ev.size(); ++i)
-      if (cs->recorded[i]) GAP_HIP(hipStreamWaitEvent(s, cs->ev[i], 0));
+      if (cs->recorded[i] && cs->on[i] != s) GAP_HIP(hipStreamWaitEvent(s, cs->ev[i], 0));
     for (hipEvent_t e : cs->ev) (void)hipEventDestroy(e);
     cs->ev.assign((size_t)k, nullptr);
     cs->recorded.assign((size_t)k, false);
+    cs->on.assign((size_t)k, nullptr);
     for (auto &e : cs->ev) GAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     cs->k = k;
     cs->next = 0;
   }
   o->slot = (int)(cs->next % (unsigned long long)k);
-  if (cs->recorded[(size_t)o->slot]) GAP_HIP(hipStreamWaitEvent(s, cs->ev[(size_t)o->slot], 0));
+  const size_t i = (size_t)o->slot;
+  if (cs->recorded[i] && cs->on[i] != s) GAP_HIP(hipStreamWaitEvent(s, cs->ev[i], 0));
   return GAP_OK;
 }
 
@@ -105,6 +110,7 @@ gap_status coop_end(int dev, hipStream_t s, CoopOrder *o) {
   CoopState *cs = coop_state(dev);
   hipError_t e = hipEventRecord(cs->ev[(size_t)o->slot], s);
   cs->recorded[(size_t)o->slot] = (e == hipSuccess);
+  cs->on[(size_t)o->slot] = s;
   cs->next += 1;
   o->lock.unlock();
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");

@@ -74,7 +74,7 @@ struct Ctl {
   GroupSlot grp[kGroups];    // barrier of the whole grid
   GroupSlot top;
   GenFlag gen[kGroups];
-  GroupSlot sgrp[kGroups];   // barrier of the small group (first kGroups workgroups)
+  GroupSlot sgrp[kGroups];   // barrier of the small group (its first workgroups)
   GroupSlot stop;
   GenFlag sgen[kGroups];
   ParkState park;
@@ -93,7 +93,7 @@ struct Ctl {
 
 struct Params {
   int32_t alpha, beta, direction, hub, chunk;
-  int32_t small;  // top-down levels with |F| and m_f at most this run on kGroups workgroups
+  int32_t small;  // top-down levels with |F| and m_f at most this run on the small group
 };
 
 enum Dir : int32_t { kTopDown = 1, kBottomUp = 2 };
