@@ -1,6 +1,8 @@
 /*
  * gapbfs.h -- C ABI of libgapbfs.so: direction-optimizing breadth-first
- * search on one AMD Instinct MI355X (gfx950).
+ * search on one AMD Instinct MI355X (gfx950), and the kernels of the same
+ * suite built on the traversal: betweenness centrality (gap_bc), shortest
+ * paths (gap_sssp) and connected components (gap_cc).
  *
  * The operation is the BFS kernel of the GAP Benchmark Suite (Beamer,
  * Asanovic, Patterson, arXiv 1508.03619):
@@ -195,8 +197,8 @@ gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
  *   stream       queue for the work
  * fp64 throughout.  Sums are formed in an order that depends on scheduling,
  * so results may differ from run to run in the last bits.  Per-call scratch
- * (about 32 bytes per vertex plus 8 bytes per 512 adjacency entries) comes
- * from the per-stream pool.  The call waits on the stream once per source
+ * (about 30 bytes per vertex, 34 when directed, plus 0.08 bytes per
+ * adjacency entry) comes from the per-stream pool.  The call waits on the stream once per source
  * (to size the per-depth arrays) and returns with the last source's work
  * queued.
  * Errors: GAP_EINVAL (NULL argument, no sources, a source out of range, an
@@ -220,7 +222,7 @@ gap_status gap_bc(const gap_graph *g, const int32_t *sources,
  *           gives the same distances (the answer is unique); delta is the
  *           one parameter the paper lets depend on the graph (Section 2.3)
  *   stream  queue for the work; the call only queues it
- * Scratch (about 16 bytes per vertex plus 1 byte per adjacency entry) comes
+ * Scratch (about 32 bytes per vertex plus 1 byte per adjacency entry) comes
  * from the per-stream pool.
  * Errors: GAP_EINVAL (NULL argument, source out of range, (n - 1) times
  * the largest weight not below 2^32 - 1), GAP_ENOMEM, GAP_EDEVICE,
@@ -244,7 +246,7 @@ gap_status gap_sssp_ex(const gap_graph *g, int32_t source, uint32_t *dist,
  *           component (so the labelling is unique)
  *   stream  queue for the work; the call waits on it once (to read a
  *           sample of roots) and returns with the rest queued
- * Scratch (8 bytes per 32 adjacency entries) comes from the per-stream
+ * Scratch (about 0.3 bytes per adjacency entry) comes from the per-stream
  * pool.  Errors: GAP_EINVAL (NULL argument), GAP_ENOMEM, GAP_EDEVICE.
  */
 gap_status gap_cc(const gap_graph *g, int32_t *labels, void *stream);
