@@ -84,14 +84,22 @@ struct CcArgs {
   int32_t skip;  // vertices whose root is this one do not walk their lists
 };
 
-// Vertex u hooked to its first kSampleRounds list entries.
+// Vertex u hooked to its first kSampleRounds list entries when they are
+// smaller than u (lists are ascending, so a vertex whose first entry is
+// larger is a local minimum and is left for its neighbours to find).  Only
+// hooking towards smaller vertices keeps the compare-and-swaps of this pass
+// on the hooking vertex's own tree: hooking towards larger ones made many
+// threads race for the root of the same popular vertex.
 __global__ __launch_bounds__(kCcBlock) void k_cc_sample(int64_t n, const int64_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
                                                         int32_t *parent) {
   for (int64_t u = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; u < n;
        u += (int64_t)gridDim.x * kCcBlock) {
     const int64_t beg = rp[u], deg = rp[u + 1] - beg;
-    for (int r = 0; r < kSampleRounds && r < deg; ++r) hook(parent, (int32_t)u, col[beg + r]);
+    for (int r = 0; r < kSampleRounds && r < deg; ++r) {
+      const int32_t v = col[beg + r];
+      if (v < u) hook(parent, (int32_t)u, v);
+    }
   }
 }
 
