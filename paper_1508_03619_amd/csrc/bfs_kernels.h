@@ -345,18 +345,68 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
 // (no atomics); words whose 64 vertices are all visited are skipped whole.
 // The step is bound by load latency (visited word -> row offsets ->
 // neighbours -> frontier bits), so a wave works on J words at once and
-// fetches R neighbours per vertex per round: up to R*J independent
-// neighbour loads and frontier probes are in flight per lane.  The first hit
-// in list order wins.
+// fetches a run of neighbours per vertex per round: 4 in the first round,
+// then R2 (a wave runs until its slowest vertex is done, so vertices that
+// missed four times get longer runs and the wave fewer rounds).  Runs are
+// read 16 bytes at a time (the column arrays are padded).  The first hit in
+// list order wins.
 #ifndef GAP_BU_WORDS
 #define GAP_BU_WORDS 4
 #endif
-#ifndef GAP_BU_ROUND
-#define GAP_BU_ROUND 4
+#ifndef GAP_BU_ROUND2
+#define GAP_BU_ROUND2 4
 #endif
+
+// One round over the J vertices of a lane: RR entries each from e[j] on.
+// Returns whether any of them is still searching.
+template <int J, int RR, bool STATS>
+__device__ inline bool bu_round(const int32_t *__restrict__ col, const uint64_t *fb, bool (&act)[J],
+                                int64_t (&e)[J], int32_t (&rem)[J], int32_t (&pu)[J], LaneAcc &acc) {
+  static_assert(RR % 4 == 0, "runs are read 16 bytes at a time");
+  int32_t u[J][RR];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int q = 0; q < RR / 4; ++q) {
+      i32x4_a4 w = {-1, -1, -1, -1};
+      if (act[j] && 4 * q < rem[j]) w = *reinterpret_cast<const i32x4_a4 *>(col + e[j] + 4 * q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[j][4 * q + k] = (act[j] && 4 * q + k < rem[j]) ? w[k] : -1;
+    }
+  bool hit[J][RR];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int k = 0; k < RR; ++k)
+      hit[j][k] = u[j][k] >= 0 && ((fb[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
+  bool more = false;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (!act[j]) continue;
+#pragma unroll
+    for (int k = RR - 1; k >= 0; --k)
+      if (hit[j][k]) pu[j] = u[j][k];
+    if (STATS) {  // entries up to and including the first hit
+      int used = 0;
+      for (int k = 0; k < RR && k < rem[j]; ++k) {
+        ++used;
+        if (hit[j][k]) break;
+      }
+      acc.scanned += used;
+    }
+    e[j] += RR;
+    rem[j] -= RR;
+    if (pu[j] >= 0 || rem[j] <= 0)
+      act[j] = false;
+    else
+      more = true;
+  }
+  return more;
+}
+
 // lfbm: when not NULL, LDS room for the whole frontier bitmap; the step
 // first copies F_d there and probes LDS instead of the L2-held copy.
-template <int BLOCK, bool STATS, int J = GAP_BU_WORDS, int R = GAP_BU_ROUND>
+template <int BLOCK, bool STATS, int J = GAP_BU_WORDS, int R2 = GAP_BU_ROUND2>
 __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
                         int64_t nwaves, uint64_t *lfbm = nullptr) {
   const int lane = lane_id();
@@ -389,43 +439,8 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
       }
       degv[j] = rem[j];
     }
-    bool any = true;
-    while (any) {
-      int32_t u[J][R];
-#pragma unroll
-      for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int k = 0; k < R; ++k) u[j][k] = (act[j] && k < rem[j]) ? a.g.col_in[e[j] + k] : -1;
-      bool hit[J][R];
-#pragma unroll
-      for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-          hit[j][k] = u[j][k] >= 0 && ((fb[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
-      bool more = false;
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        if (!act[j]) continue;
-        int used = 0;
-#pragma unroll
-        for (int k = R - 1; k >= 0; --k)
-          if (hit[j][k]) pu[j] = u[j][k];
-        if (STATS) {  // entries up to and including the first hit
-          for (int k = 0; k < R && k < rem[j]; ++k) {
-            ++used;
-            if (hit[j][k]) break;
-          }
-          acc.scanned += used;
-        }
-        e[j] += R;
-        rem[j] -= R;
-        if (pu[j] >= 0 || rem[j] <= 0)
-          act[j] = false;
-        else
-          more = true;
-      }
-      any = __ballot(more) != 0ull;
-    }
+    bool more = bu_round<J, 4, STATS>(a.g.col_in, fb, act, e, rem, pu, acc);
+    while (__ballot(more) != 0ull) more = bu_round<J, R2, STATS>(a.g.col_in, fb, act, e, rem, pu, acc);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const bool found = pu[j] >= 0;

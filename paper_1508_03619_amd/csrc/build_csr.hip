@@ -144,7 +144,8 @@ struct DevBuf {
 
 // One CSR from the raw pairs on the device: keys of the chosen direction(s)
 // (mode as in k_make_keys), sort, drop repeats, scatter columns, offsets.
-// Allocates *row_ptr (int64[n+1]) and *col (int32[nnz]); with d_w (raw
+// Allocates *row_ptr (int64[n+1]) and *col (int32[nnz], plus kColPad
+// entries of padding that no list covers); with d_w (raw
 // weights) also *wt_out (int32[nnz], the smallest weight of each pair).
 static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int32_t *d_w,
                            int64_t n, int64_t m, int bits, int mode, hipStream_t stream,
@@ -229,7 +230,7 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int
   int64_t *row_ptr = nullptr;
   int32_t *col = nullptr, *wt = nullptr;
   hipError_t e1 = hipMalloc(&row_ptr, sizeof(int64_t) * (size_t)(n + 1));
-  hipError_t e2 = hipMalloc(&col, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  hipError_t e2 = hipMalloc(&col, sizeof(int32_t) * (size_t)(nnz + kColPad));
   hipError_t e3 = d_w ? hipMalloc(&wt, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)) : hipSuccess;
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
     if (row_ptr) (void)hipFree(row_ptr);

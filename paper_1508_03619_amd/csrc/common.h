@@ -20,6 +20,14 @@ constexpr int32_t kIsolated = INT32_MIN;
 // and queues are segmented per group (each segment can hold n vertices).
 constexpr int kGroups = 16;
 
+// Column arrays are allocated kColPad entries longer than nnz, so a 16-byte
+// read of four list entries that starts at any entry stays inside the
+// allocation (entries past a list's end are read, then ignored).
+constexpr int kColPad = 4;
+
+// Four consecutive int32 with 4-byte alignment: one global_load_dwordx4.
+typedef int32_t i32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
 struct DevGraph {
   const int64_t *row_ptr;     // int64[n+1], out-lists (top-down)
   const int32_t *col;         // int32[nnz], each row ascending
