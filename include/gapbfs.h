@@ -244,8 +244,7 @@ gap_status gap_sssp_ex(const gap_graph *g, int32_t source, uint32_t *dist,
  *   g       graph from gap_build_csr or gap_build_csr_weighted
  *   labels  device int32[n], written: the smallest vertex of each vertex's
  *           component (so the labelling is unique)
- *   stream  queue for the work; the call waits on it once (to read a
- *           sample of roots) and returns with the rest queued
+ *   stream  queue for the work; the call only queues it
  * Scratch (about 0.3 bytes per adjacency entry) comes from the per-stream
  * pool.  Errors: GAP_EINVAL (NULL argument), GAP_ENOMEM, GAP_EDEVICE.
  */

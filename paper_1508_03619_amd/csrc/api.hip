@@ -394,7 +394,6 @@ gap_status workspace_reserve_cc(Workspace *ws, size_t bytes) {
     GAP_HIP(hipMalloc(&ws->cc_buf, bytes));
     ws->cc_bytes = bytes;
   }
-  if (!ws->cc_host) GAP_HIP(hipHostMalloc(&ws->cc_host, 4096));
   return GAP_OK;
 }
 

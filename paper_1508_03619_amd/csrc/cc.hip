@@ -18,17 +18,23 @@
 // Most edges need no hook: they join vertices already in one tree.  So the
 // edges are taken in two steps (the sampling scheme of GPU union-find
 // codes): first every vertex is hooked to its first kSampleRounds list
-// entries and the forest is flattened; the most frequent root among
-// kSample spread-out vertices names the giant tree; then only vertices
+// entries (where they are smaller than it) and the forest is flattened
+// after each round.  These sampling links are plain stores, not
+// compare-and-swaps: concurrent links of one root overwrite each other, so
+// some are lost, but every stored pointer goes to a smaller vertex of the
+// same component, so the forest stays acyclic and sound, and the pass
+// that follows is complete on its own.  (A compare-and-swap round here
+// took over a millisecond at scale 22: the dies' L2 copies of a root
+// stayed stale after a memory-side swap, so most swaps failed and retried
+// on a few hot roots.)  The most frequent root among
+// kSample spread-out vertices names the giant tree (found on the device,
+// so the call never waits for the host); then only vertices
 // outside it walk their lists (all entries, and for a directed graph its
 // in-list too, so an edge from the giant tree into a small one is seen
 // from the small end).  Skipping the giant tree's vertices is safe for any
 // choice of it: an edge to a vertex outside it is hooked from that end.
 // Lists of up to kLight entries are walked by one lane each; longer lists
 // become chunk items of kChunk entries walked by a whole wave.
-
-#include <algorithm>
-#include <vector>
 
 #include "runtime.h"
 
@@ -38,13 +44,25 @@ namespace {
 constexpr int kCcBlock = 256;
 constexpr int kLight = 32;
 constexpr int kChunk = 256;
-constexpr int kSampleRounds = 2;
+#ifndef GAP_CC_SAMPLE_ROUNDS
+#define GAP_CC_SAMPLE_ROUNDS 2
+#endif
+constexpr int kSampleRounds = GAP_CC_SAMPLE_ROUNDS;
 constexpr int kSample = 1024;
 
-__global__ __launch_bounds__(kCcBlock) void k_cc_init(int64_t n, int32_t *__restrict__ parent) {
+// First sampling round fused with the initialisation: each vertex starts
+// as its own root and is hooked under its first list entry (the smallest
+// neighbour, lists being ascending) when that is smaller.  No other thread
+// writes parent[v] here, and parents only decrease, so no cycle forms.
+__global__ __launch_bounds__(kCcBlock) void k_cc_init(int64_t n, const int64_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col,
+                                                      int32_t *__restrict__ parent) {
   for (int64_t v = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kCcBlock)
-    parent[v] = (int32_t)v;
+       v += (int64_t)gridDim.x * kCcBlock) {
+    const int64_t beg = rp[v];
+    const int32_t first = rp[v + 1] > beg ? col[beg] : (int32_t)v;
+    parent[v] = first < (int32_t)v ? first : (int32_t)v;
+  }
 }
 
 __device__ inline int32_t find_root(int32_t *parent, int32_t x) {
@@ -74,6 +92,16 @@ __device__ inline void hook(int32_t *parent, int32_t u, int32_t v) {
   }
 }
 
+// A sampling link: the larger of the two roots is pointed at the smaller
+// with a plain store (one attempt; a lost race loses the link).
+__device__ inline void link_sample(int32_t *parent, int32_t u, int32_t v) {
+  const int32_t ru = find_root(parent, u), rv = find_root(parent, v);
+  if (ru > rv)
+    parent[ru] = rv;
+  else if (rv > ru)
+    parent[rv] = ru;
+}
+
 struct CcArgs {
   int64_t n;
   const int64_t *rp;
@@ -81,24 +109,21 @@ struct CcArgs {
   int32_t *parent;
   int2 *items;
   unsigned int *nitems;
-  int32_t skip;  // vertices whose root is this one do not walk their lists
+  const int32_t *skip;  // vertices whose root is *skip do not walk their lists
 };
 
-// Vertex u hooked to its first kSampleRounds list entries when they are
-// smaller than u (lists are ascending, so a vertex whose first entry is
-// larger is a local minimum and is left for its neighbours to find).  Only
-// hooking towards smaller vertices keeps the compare-and-swaps of this pass
-// on the hooking vertex's own tree: hooking towards larger ones made many
-// threads race for the root of the same popular vertex.
+// Sampling round r >= 1: vertex u linked to list entry r when it is
+// smaller than u (lists are ascending, so a vertex whose entries are larger
+// is a local minimum and is left for its neighbours to find).
 __global__ __launch_bounds__(kCcBlock) void k_cc_sample(int64_t n, const int64_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
-                                                        int32_t *parent) {
+                                                        int32_t *parent, int r) {
   for (int64_t u = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; u < n;
        u += (int64_t)gridDim.x * kCcBlock) {
     const int64_t beg = rp[u], deg = rp[u + 1] - beg;
-    for (int r = 0; r < kSampleRounds && r < deg; ++r) {
+    if (r < deg) {
       const int32_t v = col[beg + r];
-      if (v < u) hook(parent, (int32_t)u, v);
+      if (v < u) link_sample(parent, (int32_t)u, v);
     }
   }
 }
@@ -106,11 +131,12 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_sample(int64_t n, const int64_t
 // Short lists of vertices outside the giant tree, one lane each; long
 // lists become chunk items.
 __global__ __launch_bounds__(kCcBlock) void k_cc_light(CcArgs a) {
+  const int32_t giant = *a.skip;
   const int64_t stride = (int64_t)gridDim.x * kCcBlock;
   const int64_t n_round = (a.n + stride - 1) / stride * stride;  // whole waves iterate together
   for (int64_t u = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; u < n_round; u += stride) {
     int64_t beg = 0, deg = 0;
-    if (u < a.n && find_root(a.parent, (int32_t)u) != a.skip) {
+    if (u < a.n && find_root(a.parent, (int32_t)u) != giant) {
       beg = a.rp[u];
       deg = a.rp[u + 1] - beg;
     }
@@ -142,11 +168,55 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_heavy(CcArgs a) {
   }
 }
 
-// The roots of kSample vertices spread over the vertex range.
-__global__ void k_cc_pick(int64_t n, const int32_t *__restrict__ parent, int32_t *out) {
-  for (int i = threadIdx.x; i < kSample; i += blockDim.x) {
-    const int64_t v = (int64_t)(((uint64_t)i * 2654435761ull + 12345ull) % (uint64_t)n);
-    out[i] = parent[v];
+// The giant tree: the most frequent root among kSample vertices spread over
+// the vertex range (the smallest such root on a tie), by one workgroup:
+// the roots are sorted in LDS (bitonic network), the thread at the start
+// of each run finds the run's end by bisection, and a block maximum over
+// (run length, -root) keeps the winner.
+// Thread 0 also clears the two chunk-item counters of the passes that
+// follow (a kernel, not a memset, so the call can be captured in a graph).
+__global__ __launch_bounds__(kSample) void k_cc_pick(int64_t n, const int32_t *__restrict__ parent,
+                                                     int32_t *giant, unsigned int *nitems) {
+  __shared__ int32_t key[kSample];
+  __shared__ unsigned long long wbest[kSample / kWave];
+  const int t = threadIdx.x;
+  key[t] = parent[(int64_t)(((uint64_t)t * 2654435761ull + 12345ull) % (uint64_t)n)];
+  __syncthreads();
+  for (int k = 2; k <= kSample; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int p = t ^ j;
+      if (p > t) {
+        const int32_t x = key[t], y = key[p];
+        if ((x > y) == ((t & k) == 0)) {
+          key[t] = y;
+          key[p] = x;
+        }
+      }
+      __syncthreads();
+    }
+  unsigned long long best = 0;
+  if (t == 0 || key[t - 1] != key[t]) {
+    int lo = t, hi = kSample;  // key[lo] == key[t]; hi == kSample or key[hi] != key[t]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (key[mid] == key[t])
+        lo = mid;
+      else
+        hi = mid;
+    }
+    best = ((unsigned long long)(hi - t) << 32) | (uint32_t)(INT32_MAX - key[t]);
+  }
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const unsigned long long other = __shfl_xor(best, o, kWave);
+    best = other > best ? other : best;
+  }
+  if (lane_id() == 0) wbest[t / kWave] = best;
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kSample / kWave; ++w) best = wbest[w] > best ? wbest[w] : best;
+    *giant = INT32_MAX - (int32_t)(uint32_t)best;
+    nitems[0] = 0;
+    nitems[1] = 0;
   }
 }
 
@@ -186,36 +256,21 @@ gap_status run_cc(const gap_graph *g, int32_t *labels, hipStream_t stream) {
   }
   // chunk items: sum over long lists of ceil(deg / kChunk), per list set
   const int64_t cap_items = g->nnz / kChunk + g->nnz / (kLight + 1) + 1;
-  st = workspace_reserve_cc(ws, sizeof(int2) * (size_t)cap_items + sizeof(int32_t) * kSample + 1024);
+  st = workspace_reserve_cc(ws, sizeof(int2) * (size_t)cap_items + 1024);
   if (st != GAP_OK) return st;
   char *p = reinterpret_cast<char *>(ws->cc_buf);
-  unsigned int *nitems = carve<unsigned int>(p, 1);
-  int32_t *picks = carve<int32_t>(p, kSample);
+  unsigned int *nitems = carve<unsigned int>(p, 2);  // one per pass
+  int32_t *giant = carve<int32_t>(p, 1);
   int2 *items = carve<int2>(p, cap_items);
   const int grid = di->cus * 8;
   const int64_t n = g->n;
-  k_cc_init<<<grid, kCcBlock, 0, stream>>>(n, labels);
-  k_cc_sample<<<grid, kCcBlock, 0, stream>>>(n, g->row_ptr, g->col, labels);
+  k_cc_init<<<grid, kCcBlock, 0, stream>>>(n, g->row_ptr, g->col, labels);
   k_cc_compress<<<grid, kCcBlock, 0, stream>>>(n, labels);
-  k_cc_pick<<<1, 256, 0, stream>>>(n, labels, picks);
-  GAP_HIP(hipGetLastError());
-  int32_t *h = reinterpret_cast<int32_t *>(ws->cc_host);
-  GAP_HIP(hipMemcpyAsync(h, picks, sizeof(int32_t) * kSample, hipMemcpyDeviceToHost, stream));
-  GAP_HIP(hipStreamSynchronize(stream));
-  // the most frequent root among the picks
-  std::vector<int32_t> v(h, h + kSample);
-  std::sort(v.begin(), v.end());
-  int32_t giant = v[0];
-  int best = 0;
-  for (size_t i = 0; i < v.size();) {
-    size_t j = i;
-    while (j < v.size() && v[j] == v[i]) ++j;
-    if ((int)(j - i) > best) {
-      best = (int)(j - i);
-      giant = v[i];
-    }
-    i = j;
+  for (int r = 1; r < kSampleRounds; ++r) {
+    k_cc_sample<<<grid, kCcBlock, 0, stream>>>(n, g->row_ptr, g->col, labels, r);
+    k_cc_compress<<<grid, kCcBlock, 0, stream>>>(n, labels);
   }
+  k_cc_pick<<<1, kSample, 0, stream>>>(n, labels, giant, nitems);
   // the lists of the vertices outside the giant tree: out-lists, and the
   // in-lists of a directed graph
   const int passes = g->directed ? 2 : 1;
@@ -226,9 +281,8 @@ gap_status run_cc(const gap_graph *g, int32_t *labels, hipStream_t stream) {
     a.col = pass == 0 ? g->col : g->col_in;
     a.parent = labels;
     a.items = items;
-    a.nitems = nitems;
+    a.nitems = nitems + pass;
     a.skip = giant;
-    GAP_HIP(hipMemsetAsync(nitems, 0, sizeof(unsigned int), stream));
     k_cc_light<<<grid, kCcBlock, 0, stream>>>(a);
     k_cc_heavy<<<grid, kCcBlock, 0, stream>>>(a);
   }

@@ -102,7 +102,6 @@ struct Workspace {
   // connected components
   size_t cc_bytes = 0;
   void *cc_buf = nullptr;
-  void *cc_host = nullptr;  // pinned, 4 KiB
 };
 
 Workspace *workspace_for(int dev, hipStream_t stream);

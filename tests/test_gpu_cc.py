@@ -5,7 +5,8 @@ labels must match exactly; the paper's verifier (one traversal per label,
 Section 3) also runs on the device result.  Covers every graph on 5
 vertices, random graphs with repeats and self-loops both ways (weak
 components when directed), long paths, hubs split into chunk items,
-generated graphs, repeated runs, edge cases and two streams."""
+generated graphs, repeated runs, edge cases, two streams and replays of a
+captured call."""
 import itertools
 
 import numpy as np
@@ -116,3 +117,35 @@ def test_two_streams(gpu):
         assert np.array_equal(o.cpu().numpy(), oracle.components(e.n, e.src, e.dst))
     for g in gs:
         g.free()
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_captured_graph_replays(gpu, directed):
+    """The call only queues work (no host wait, no memset), so it can be
+    captured once its stream's scratch exists; every replay, with eager
+    calls in between, gives the oracle's labels."""
+    import torch
+    from paper_1508_03619_amd import inputs
+    el = inputs.rmat(14, 8, seed=136)
+    g = gpu.build_csr(el.n, el.src, el.dst, directed=directed)
+    ref = oracle.components(el.n, el.src, el.dst)
+    st = torch.cuda.Stream()
+    labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    eager = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    gpu.cc(g, labels, stream=st)  # sizes the stream's scratch
+    st.synchronize()
+    say(f"cc: graph capture directed={directed}")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=st):
+        gpu.cc(g, labels, stream=st)
+    for _ in range(3):
+        labels.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(labels.cpu().numpy(), ref)
+        gpu.cc(g, eager, stream=st)
+        st.synchronize()
+        assert np.array_equal(eager.cpu().numpy(), ref)
+    del graph
+    g.free()
