@@ -29,15 +29,21 @@
 namespace gap {
 namespace {
 
-// Workgroups per CU of the persistent grid.  The occupancy query reports 7
-// for this kernel, but with 7 per CU the first grid barrier timed out (not
-// every workgroup was resident); 4 (16 waves per CU, as in the other
-// persistent kernels) completes.
+// The persistent grid: one workgroup of 1024 threads per CU (16 waves, as
+// in the search kernel).  Every phase ends at a grid barrier, and its cost
+// grows with the number of arriving workgroups: 4 workgroups of 256 per CU
+// put a floor of about 27 us under every phase, and 1024-thread groups cut
+// a search by 4-16 % (more where the bucket width is small and phases are
+// many).  Cooperative grids must be resident as a whole: the occupancy
+// query reported 7 workgroups of 256 per CU once, but with 7 the first
+// barrier timed out, so the count is capped, never taken from the query.
 #ifndef GAP_SSSP_BLOCKS_PER_CU
-#define GAP_SSSP_BLOCKS_PER_CU 4
+#define GAP_SSSP_BLOCKS_PER_CU 1
 #endif
-
-constexpr int kSpBlock = 256;
+#ifndef GAP_SSSP_BLOCK
+#define GAP_SSSP_BLOCK 1024
+#endif
+constexpr int kSpBlock = GAP_SSSP_BLOCK;
 constexpr int kSlice = 16;      // list entries per near item
 constexpr int kItemLanes = 4;   // lanes per item (kSlice / kItemLanes entries each)
 constexpr uint32_t kInf = 0xFFFFFFFFu;
