@@ -120,6 +120,18 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
       if (!grid_sync(a.ctl, nblocks, Totals{}, -1, 0)) return;
       have_bm = true;
     }
+    if (dir == kBottomUp && ndir == kTopDown) {
+      // the bottom-up steps left F_d as a bitmap only: queue it for this
+      // top-down step (buffer set d & 1), on the workgroups that run it
+      StepArgs c{a.g, a.parent, a.depth, a.Q, (d & 1) ^ 1, a.ctl, nullptr, nullptr, nullptr,
+                 d, a.p.hub, a.p.chunk};
+      queue_from_bitmap<BLOCK>(c, st, (fsel ? a.bm1 : a.bm0), gwave,
+                               small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
+      int unused = 0;
+      if (!grid_sync_x(a.ctl, small ? small_barrier(a.ctl) : main_barrier(a.ctl),
+                       small ? nsmall : nblocks, Totals{}, d & 1, d & 1, NoDecision{}, unused))
+        return;
+    }
     if (ndir == kTopDown) have_bm = false;
     dir = ndir;
     if (STATS && tid == 0 && d < a.max_recs) {
@@ -138,8 +150,9 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     if (dir == kTopDown)
       td_step<BLOCK, STATS>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
     else
-      bu_step<BLOCK, STATS>(s, st, acc, gwave, nwaves,  // never on the small group
-                            a.lds_bm ? lds_fbm : nullptr);
+      bu_step<BLOCK, STATS, GAP_BU_WORDS, GAP_BU_ROUND2, false>(s, st, acc, gwave,
+                                                                nwaves,  // never on the small group
+                                                                a.lds_bm ? lds_fbm : nullptr);
     const Totals t = step_end<BLOCK>(s, st, acc);
     const int fsel_next = (dir == kBottomUp) ? (fsel ^ 1) : fsel;
     const SmallDecision dec{a.g.n, mu, nv, (int64_t)a.p.small, dir, d, have_bm ? 1 : 0, fsel_next,

@@ -406,7 +406,10 @@ __device__ inline bool bu_round(const int32_t *__restrict__ col, const uint64_t 
 
 // lfbm: when not NULL, LDS room for the whole frontier bitmap; the step
 // first copies F_d there and probes LDS instead of the L2-held copy.
-template <int BLOCK, bool STATS, int J = GAP_BU_WORDS, int R2 = GAP_BU_ROUND2>
+// QUEUE: also append F_{d+1} to the vertex queue (and hub chunk items); a
+// caller that passes false only counts the totals, and turns the bitmap
+// into a queue itself when a top-down step follows (queue_from_bitmap).
+template <int BLOCK, bool STATS, int J = GAP_BU_WORDS, int R2 = GAP_BU_ROUND2, bool QUEUE = true>
 __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
                         int64_t nwaves, uint64_t *lfbm = nullptr) {
   const int lane = lane_id();
@@ -457,9 +460,74 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
         a.nbm[base + j] = b;
         if (b) a.vbm[base + j] = vis[j] | b;
       }
-      stage_append<BLOCK>(a, st, found, (int32_t)v, (int64_t)degv[j], acc);
+      if (QUEUE) {
+        stage_append<BLOCK>(a, st, found, (int32_t)v, (int64_t)degv[j], acc);
+      } else if (found) {
+        acc.mf += (unsigned long long)degv[j];
+        acc.nv += 1;
+      }
     }
   }
+}
+
+// Position of the k-th set bit (k from 0) of x, which has more than k.
+__device__ inline int nth_set_bit(uint64_t x, uint32_t k) {
+  int pos = 0;
+#pragma unroll
+  for (int half = 32; half >= 1; half >>= 1) {
+    const uint32_t c = (uint32_t)__popcll(x & ((1ull << half) - 1ull));
+    if (k >= c) {
+      k -= c;
+      x >>= half;
+      pos += half;
+    }
+  }
+  return pos;
+}
+
+// Bottom-up -> top-down: F_d, held as a bitmap by the bottom-up steps
+// (which do not build queues), becomes the vertex queue and hub chunk
+// items of buffer set bs_out, as a top-down step would have appended them.
+// A wave loads 64 bitmap words at once and hands their set bits to its
+// lanes in order (prefix sums of the word popcounts), so a sparse frontier
+// costs a few round trips per wave even on the small group.  Whole
+// workgroups; the staged entries reach the segments in step_end, and a
+// barrier that publishes bs_out must follow.
+template <int BLOCK>
+__device__ void queue_from_bitmap(const StepArgs &a, Stage<BLOCK> &st, const uint64_t *fbm,
+                                  int64_t gwave, int64_t nwaves) {
+  if (threadIdx.x == 0) {
+    st.qn = 0;
+    st.cn = 0;
+  }
+  __syncthreads();
+  LaneAcc acc;
+  const int lane = lane_id();
+  const int64_t nwords = (a.g.n + kWave - 1) / kWave;
+  for (int64_t w0 = gwave * kWave; w0 < nwords; w0 += nwaves * kWave) {
+    const uint64_t bits = w0 + lane < nwords ? fbm[w0 + lane] : 0ull;
+    uint32_t total;
+    const uint32_t off = wave_excl_scan_u32((uint32_t)__popcll(bits), total);
+    for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+      const uint32_t i = i0 + (uint32_t)lane;
+      int j = 0;  // the word holding set bit i: largest j with off_j <= i
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const uint32_t oc = __shfl(off, j + step, kWave);
+        if (oc <= i) j += step;
+      }
+      const uint64_t bj = __shfl(bits, j, kWave);
+      const uint32_t oj = __shfl(off, j, kWave);
+      const bool in = i < total;
+      int64_t v = 0, degv = 0;
+      if (in) {
+        v = (w0 + j) * kWave + nth_set_bit(bj, i - oj);
+        degv = a.g.row_ptr[v + 1] - a.g.row_ptr[v];
+      }
+      stage_append<BLOCK>(a, st, in, (int32_t)v, degv, acc);
+    }
+  }
+  (void)step_end<BLOCK>(a, st, acc);
 }
 
 // Top-down -> bottom-up: build the frontier bitmap (depth == d) and the
