@@ -51,7 +51,8 @@ def algorithmic_bytes(recs, n, directed=False) -> int:
         4|F| queue + 16|F| row_ptr + 4 N_F col + 4 N_F parent probes + 12|C|
     bottom-up level, U unvisited, S_U scanned entries, H found:
         16|U| row_ptr + 4 S_U col + 3 n/8 bitmaps + 8|H|
-    switch to bottom-up: 4|F| + n/8; final pass: 8n
+    switch to bottom-up: 4|F| + n/8; switch back to top-down (the frontier
+    bitmap becomes the queue): 20|F| + n/8; final pass: 8n
     directed graphs add, per bottom-up level, 16|H| for the out-degrees of
     the found vertices, and at the switch 16|U| for the in-degree test
     """
@@ -59,6 +60,8 @@ def algorithmic_bytes(recs, n, directed=False) -> int:
     prev_dir = 1
     for r in recs:
         if r["direction"] == 1:
+            if prev_dir == 2:
+                total += 20 * r["frontier"] + n // 8
             total += 20 * r["frontier"] + 8 * r["frontier_edges"] + 12 * r["claimed"]
         else:
             if prev_dir == 1:

@@ -36,3 +36,10 @@ def test_algorithmic_bytes_model():
     want_bu2 = 16 * 500 + 4 * 900 + 3 * n // 8 + 8 * 300
     assert bench.algorithmic_bytes([td, bu, bu], n) == (base + 20 * 10 + 8 * 100 + 12 * 40 + want_bu
                                                        + want_bu2)
+    # back to top-down: the frontier bitmap becomes the queue (20 per
+    # frontier vertex + n/8), then the top-down level itself
+    td2 = {"direction": 1, "frontier": 30, "frontier_edges": 60, "claimed": 5,
+           "scanned": 60, "unvisited": 0}
+    want_td2 = 20 * 30 + n // 8 + 20 * 30 + 8 * 60 + 12 * 5
+    assert bench.algorithmic_bytes([td, bu, td2], n) == (base + 20 * 10 + 8 * 100 + 12 * 40 + want_bu
+                                                        + want_td2)
