@@ -26,13 +26,21 @@ struct Queues {
 // with one LDS atomic; the workgroup copies the slots out with one device
 // atomic per segment at the end of the step.  Slots beyond the capacity go
 // straight to the segment (reserved with a device atomic).
+// Hub claims are listed as {vertex, chunk count} and expanded into chunk
+// items by the whole workgroup at the end of the step.
 template <int BLOCK>
 struct Stage {
   static constexpr int QCAP = BLOCK * 8;
   static constexpr int CCAP = 256;
+  static constexpr int HCAP = BLOCK;
   int32_t q[QCAP];
   int2 c[CCAP];
-  unsigned int qn, cn;
+  int32_t hv[HCAP];
+  uint32_t hch[HCAP];  // chunk items of each hub claim, then their offsets
+  uint32_t hwave[BLOCK / kWave];
+  unsigned int qn, cn, hn;
+  unsigned int hbase;
+  unsigned long long hgbase;
   unsigned long long qbase, cbase;
   unsigned long long qpre[kGroups + 1];  // input segment prefix sums
   unsigned long long cpre[kGroups + 1];
@@ -145,6 +153,83 @@ __device__ inline void stage_chunks(const StepArgs &a, Stage<BLOCK> &st, bool wa
   }
 }
 
+// Lists hub claims {v, chunk count} for expand_hubs; claims beyond the
+// list's capacity are expanded by the wave at once.
+template <int BLOCK>
+__device__ inline void stage_hubs(const StepArgs &a, Stage<BLOCK> &st, bool want, int32_t v,
+                                  int64_t degv) {
+  const uint64_t mb = __ballot(want);
+  if (!mb) return;
+  const int lane = lane_id();
+  const int leader = first_lane(mb);
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(&st.hn, (unsigned int)__popcll(mb));
+  base = __shfl(base, leader, kWave);
+  const unsigned int slot = base + lane_rank(mb);
+  const bool fits = want && slot < (unsigned int)Stage<BLOCK>::HCAP;
+  if (fits) {
+    st.hv[slot] = v;
+    st.hch[slot] = (uint32_t)((degv + a.chunk - 1) / a.chunk);
+  }
+  stage_chunks<BLOCK>(a, st, want && !fits, v, degv, 0);
+}
+
+// Whole workgroup, after a barrier: the listed hub claims become chunk
+// items (staged like stage_chunks's, so step_end copies them out).  The
+// claiming wave alone would write a hub frontier's items one after another
+// (R-MAT 22's first levels claim thousands of hubs, ~10 items each).
+template <int BLOCK>
+__device__ inline void expand_hubs(const StepArgs &a, Stage<BLOCK> &st) {
+  const unsigned int hn0 = st.hn;
+  if (hn0 == 0) return;  // uniform: read after a barrier
+  const unsigned int hn = hn0 < (unsigned int)Stage<BLOCK>::HCAP ? hn0 : Stage<BLOCK>::HCAP;
+  const int t = threadIdx.x;
+  const int wv = t / kWave;
+  const uint32_t mine = (unsigned int)t < hn ? st.hch[t] : 0u;  // HCAP == BLOCK: one per thread
+  uint32_t wtot = 0;
+  uint32_t off = wave_excl_scan_u32(mine, wtot);
+  if (lane_id() == 0) st.hwave[wv] = wtot;
+  __syncthreads();
+  uint32_t total = 0;
+  for (int w = 0; w < BLOCK / kWave; ++w) {
+    if (w < wv) off += st.hwave[w];
+    total += st.hwave[w];
+  }
+  if ((unsigned int)t < hn) st.hch[t] = off;  // only thread t reads hch[t] above
+  const int g = (int)(blockIdx.x % kGroups);
+  const int bs_out = a.bs_in ^ 1;
+  const unsigned int cap = Stage<BLOCK>::CCAP;
+  if (t == 0) {
+    const unsigned int base = atomicAdd(&st.cn, total);
+    const unsigned int ov_start = base > cap ? base : cap;
+    const unsigned int n_ov = base + total > cap ? base + total - ov_start : 0u;
+    st.hbase = base;
+    st.hgbase = n_ov ? atomicAdd(&a.ctl->seg[bs_out][g].c, (unsigned long long)n_ov) : 0ull;
+    st.hn = 0;
+  }
+  __syncthreads();
+  const unsigned int base = st.hbase;
+  const unsigned int ov_start = base > cap ? base : cap;
+  const unsigned long long gbase = st.hgbase;
+  for (uint32_t i = (uint32_t)t; i < total; i += BLOCK) {
+    uint32_t lo = 0, hi = hn;  // the claim whose range holds item i (every hub has items)
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (st.hch[mid] <= i)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int2 item = make_int2(st.hv[lo], (int)(i - st.hch[lo]));
+    const unsigned int slot = base + i;
+    if (slot < cap)
+      st.c[slot] = item;
+    else
+      a.Q.cs(bs_out)[g * a.Q.ccap + (int64_t)(gbase + (slot - ov_start))] = item;
+  }
+  __syncthreads();
+}
+
 // Appends this wave's newly reached vertices to F_{d+1}: degree <= hub ->
 // vertex queue, larger -> chunk items so that one hub is expanded by many
 // waves; accumulates the frontier totals.
@@ -154,7 +239,7 @@ __device__ inline void stage_append(const StepArgs &a, Stage<BLOCK> &st, bool cl
   if (__ballot(claimed) == 0ull) return;
   const bool big = claimed && degv > a.hub;
   stage_vertices<BLOCK>(a, st, claimed && !big, v);
-  stage_chunks<BLOCK>(a, st, big, v, degv, 0);
+  stage_hubs<BLOCK>(a, st, big, v, degv);
   if (claimed) {
     acc.mf += (unsigned long long)degv;
     acc.nv += 1;
@@ -181,6 +266,7 @@ __device__ inline void step_begin(const StepArgs &a, Stage<BLOCK> &st) {
     if (lane == 0) {
       st.qn = 0;
       st.cn = 0;
+      st.hn = 0;
     }
   }
   __syncthreads();
@@ -188,8 +274,9 @@ __device__ inline void step_begin(const StepArgs &a, Stage<BLOCK> &st) {
 
 // End of a step (all threads): copy staged vertices to this group's
 // segments (one device atomic per segment per workgroup) and reduce the
-// workgroup's totals into thread 0.
-template <int BLOCK>
+// workgroup's totals into thread 0.  HUBS: the step listed hub claims
+// (stage_append does; callers that stage chunks directly pass false).
+template <int BLOCK, bool HUBS = true>
 __device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc) {
   const int wv = threadIdx.x / kWave;
   // a wave that counted nothing (most waves of a small level) skips the
@@ -209,6 +296,7 @@ __device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &
     st.part[wv][3] = s3;
   }
   __syncthreads();
+  if (HUBS) expand_hubs<BLOCK>(a, st);
   const int g = (int)(blockIdx.x % kGroups);
   const int bs_out = a.bs_in ^ 1;
   const unsigned int nq = st.qn < (unsigned)Stage<BLOCK>::QCAP ? st.qn : Stage<BLOCK>::QCAP;
@@ -275,6 +363,12 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
   const int lane = lane_id();
   const int2 *cin = a.Q.cs(a.bs_in);
   const int32_t *qin = a.Q.qs(a.bs_in);
+  // Work goes round the workgroups first (item i to wave i / nblk of
+  // workgroup i % nblk), so the items of a small frontier, and the claims
+  // they make, spread over every workgroup's staging and hub list.
+  constexpr int kWpb = BLOCK / kWave;
+  const int64_t nblk = nwaves / kWpb;
+  gwave = (gwave % kWpb) * nblk + gwave / kWpb;
   const unsigned long long nc = st.cpre[kGroups];
   for (unsigned long long ci = (unsigned long long)gwave; ci < nc; ci += (unsigned long long)nwaves) {
     const int h = seg_of(ci, st.cpre);
@@ -499,6 +593,7 @@ __device__ void queue_from_bitmap(const StepArgs &a, Stage<BLOCK> &st, const uin
   if (threadIdx.x == 0) {
     st.qn = 0;
     st.cn = 0;
+    st.hn = 0;
   }
   __syncthreads();
   LaneAcc acc;

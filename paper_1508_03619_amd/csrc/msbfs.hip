@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
       stage_chunks<kMsBlock>(sa, sh.st, any && big, (int32_t)vv, deg, 0);
       stage_chunks<kMsBlock>(sa, sh.st, incomplete && big, (int32_t)vv, deg, kBuFlag);
     }
-    (void)step_end<kMsBlock>(sa, sh.st, none);
+    (void)step_end<kMsBlock, false>(sa, sh.st, none);
     __syncthreads();
     for (int s = threadIdx.x; s < nseg; s += kMsBlock) {
       MsSegTotals &T = a.ctl->tot[d & 1][s];
