@@ -148,7 +148,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     step_begin<BLOCK>(s, st);
     LaneAcc acc;
     if (dir == kTopDown)
-      td_step<BLOCK, STATS>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
+      td_step<BLOCK, STATS, true>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
     else
       bu_step<BLOCK, STATS, GAP_BU_WORDS, GAP_BU_ROUND2, false>(s, st, acc, gwave,
                                                                 nwaves,  // never on the small group
