@@ -124,7 +124,12 @@ def test_hub_splitting_and_tuning_invariance(gpu):
                 dict(hub_degree=4096, chunk_edges=1024), dict(alpha=1, beta=1),
                 dict(alpha=1000, beta=1000), dict(alpha=2, beta=200),
                 dict(block=512), dict(block=1024), dict(block=256, blocks_per_cu=1),
-                dict(block=1024, blocks_per_cu=1)]
+                dict(block=1024, blocks_per_cu=1),
+                # hub claims (listed per workgroup, and beyond the list's
+                # capacity) in levels that switch direction often, so the
+                # frontier bitmap is turned back into a queue with hubs in it
+                dict(hub_degree=1, chunk_edges=64, alpha=2, beta=200),
+                dict(hub_degree=8, chunk_edges=64, alpha=1, beta=1)]
     for src in srcs:
         ref = A.bfs(src)[0]
         for st in settings:
