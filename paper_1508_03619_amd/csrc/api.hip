@@ -303,13 +303,13 @@ gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const
   for (auto &b : ws->bm)
     if (e == hipSuccess) e = hipMalloc(&b, sizeof(uint64_t) * (size_t)words);
   if (e == hipSuccess) e = hipMalloc(&ws->depth_scratch, sizeof(int32_t) * (size_t)cap_n);
-  if (e == hipSuccess) e = hipMalloc(&ws->ctl, sizeof(Ctl));
+  if (e == hipSuccess) e = hipMalloc(&ws->ctl, 2 * sizeof(Ctl));
   if (e == hipSuccess) e = hipMalloc(&ws->dd_args, kArgsBytes);
   if (e == hipSuccess) e = hipHostMalloc(&ws->h_flags, 4 * sizeof(int));
   if (e == hipSuccess) e = hipHostMalloc(&ws->h_args, kArgsBytes);
   // on the workspace's stream: a null-stream memset is not ordered before
   // work on a non-blocking stream
-  if (e == hipSuccess) e = hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), ws->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ws->ctl, 0, 2 * sizeof(Ctl), ws->stream);
 
   if (e != hipSuccess) {
     release_single(ws);
@@ -317,6 +317,8 @@ gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const
   }
   ws->cap_n = cap_n;
   ws->cap_chunks = cap_c;
+  ws->ctl_seq = 0;
+  ws->ctl_next_clean = true;
   return GAP_OK;
 }
 

@@ -23,6 +23,7 @@ struct SearchArgs {
   uint64_t *bm0, *bm1;  // frontier bitmaps (current / next alternate)
   uint64_t *vbm;
   Ctl *ctl;
+  Ctl *ctl_clear;  // persistent kernel: the next search's control block, cleared at start
   Params p;
   DevLevelRec *recs;
   int32_t max_recs;
@@ -88,6 +89,10 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   const bool small_enabled = a.p.small > 0 && nblocks > nsmall;
 
   init_vertices(a.g, a.parent, a.depth, a.source, tid, nthreads);
+  if (a.ctl_clear) {  // no search uses it now: the one before this has finished with it
+    uint32_t *w = reinterpret_cast<uint32_t *>(a.ctl_clear);
+    for (int64_t i = tid; i < (int64_t)(sizeof(Ctl) / sizeof(uint32_t)); i += nthreads) w[i] = 0u;
+  }
   Totals part = {};
   if (tid == 0) part = init_source(a.g, a.Q, a.ctl, a.source, a.p.hub, a.p.chunk);
   if (!grid_sync(a.ctl, nblocks, part, 0, 0)) return;
@@ -387,10 +392,12 @@ static gap_status enqueue_level(DDArgs *dA, int grid, bool stats, hipStream_t st
 }
 
 // Reads err, levels and done from the device (synchronous).
-static gap_status read_flags(Workspace *ws, hipStream_t stream, int *done, int *levels, int *err) {
+static gap_status read_flags(Workspace *ws, const Ctl *ctl, hipStream_t stream, int *done,
+                             int *levels, int *err) {
   static_assert(offsetof(Ctl, levels) == offsetof(Ctl, err) + sizeof(int), "Ctl layout");
   static_assert(offsetof(Ctl, done) == offsetof(Ctl, err) + 2 * sizeof(int), "Ctl layout");
-  GAP_HIP(hipMemcpyAsync(ws->h_flags, &ws->ctl->err, 3 * sizeof(int), hipMemcpyDeviceToHost,
+  static_assert(sizeof(Ctl) % sizeof(uint32_t) == 0, "Ctl is cleared word by word");
+  GAP_HIP(hipMemcpyAsync(ws->h_flags, &ctl->err, 3 * sizeof(int), hipMemcpyDeviceToHost,
                          stream));
   GAP_HIP(hipStreamSynchronize(stream));
   *err = ws->h_flags[0];
@@ -421,7 +428,7 @@ static gap_status run_device_driven(const SearchArgs &a, const gap_params &p, bo
   int done = 0, levels = 0, err = 0;
   if (p.mode == GAP_MODE_LEVELS) {
     for (int64_t it = 0;; ++it) {
-      gap_status st = read_flags(ws, stream, &done, &levels, &err);
+      gap_status st = read_flags(ws, ws->ctl, stream, &done, &levels, &err);
       if (st != GAP_OK) return st;
       if (done || err) break;
       if (it > a.g.n + 1) {
@@ -456,7 +463,7 @@ static gap_status run_device_driven(const SearchArgs &a, const gap_params &p, bo
       ws->graph_grid = grid;
     }
     for (int64_t it = 0;; ++it) {
-      gap_status st = read_flags(ws, stream, &done, &levels, &err);
+      gap_status st = read_flags(ws, ws->ctl, stream, &done, &levels, &err);
       if (st != GAP_OK) return st;
       if (done || err) break;
       if (it * K > a.g.n + 1) {
@@ -516,11 +523,18 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
 
   int32_t levels = -1;
   const bool device_driven = p.mode == GAP_MODE_LEVELS || p.mode == GAP_MODE_GRAPH;
+  Ctl *used = ws->ctl;
   if (device_driven) {
+    ws->ctl_next_clean = false;  // ctl[0] is left as this schedule leaves it
+    a.ctl_clear = nullptr;
     st = run_device_driven(a, p, want_stats, ws, di, stream, &levels);
     if (st != GAP_OK) return st;
   } else {
-    GAP_HIP(hipMemsetAsync(ws->ctl, 0, sizeof(Ctl), stream));
+    used = ws->ctl + (ws->ctl_seq & 1);
+    if (!ws->ctl_next_clean) GAP_HIP(hipMemsetAsync(used, 0, sizeof(Ctl), stream));
+    ws->ctl_next_clean = false;  // until this search's kernel is queued
+    a.ctl = used;
+    a.ctl_clear = ws->ctl + ((ws->ctl_seq + 1) & 1);
     CoopOrder order;
     st = coop_begin(g->device, stream, p.grid_split, &order);
     if (st != GAP_OK) return st;
@@ -529,10 +543,12 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
     gap_status st2 = coop_end(g->device, stream, &order);
     if (st != GAP_OK) return st;
     if (st2 != GAP_OK) return st2;
+    ws->ctl_seq += 1;
+    ws->ctl_next_clean = true;
   }
   if (want_stats) {
     int done = 0, err = 0, lv = 0;
-    st = read_flags(ws, stream, &done, &lv, &err);
+    st = read_flags(ws, used, stream, &done, &lv, &err);
     if (st != GAP_OK) return st;
     if (err != 0) {
       set_error(err == GAP_ETIMEOUT ? "device-side wait timed out (grid barrier)"

@@ -75,7 +75,13 @@ struct Workspace {
   int2 *cq[2] = {nullptr, nullptr};
   uint64_t *bm[3] = {nullptr, nullptr, nullptr};  // frontier A, frontier B, visited
   int32_t *depth_scratch = nullptr;
+  // Two control blocks.  The per-level schedules use ctl[0] (reset by a
+  // memset before each search).  Persistent searches alternate: search k
+  // runs on ctl[k & 1] and its kernel clears the other block, which the
+  // search before it has finished with, for search k + 1.
   Ctl *ctl = nullptr;
+  uint64_t ctl_seq = 0;          // persistent searches queued
+  bool ctl_next_clean = false;   // ctl[ctl_seq & 1] is being or has been cleared
   int *h_flags = nullptr;  // pinned readback of err, levels, done
   void *dd_args = nullptr; // device copy of the per-search arguments
   void *h_args = nullptr;  // pinned staging of the same
