@@ -143,8 +143,11 @@ gap_status gap_graph_export_in(const gap_graph *g, int64_t *row_ptr,
  * (persistent-kernel) schedule the call only queues work; with the
  * host-driven schedule it waits on the stream between levels.
  * Errors: GAP_EINVAL (NULL g or parent, source out of range),
- * GAP_ENOMEM, GAP_EDEVICE, GAP_ETIMEOUT (reported by the next call on the
- * stream or by gap_bfs_ex with stats).
+ * GAP_ENOMEM, GAP_EDEVICE, GAP_ETIMEOUT (a device-side wait that timed
+ * out: reported by gap_bfs_ex with stats and by the host-driven schedule,
+ * which wait for the search; the default schedule returns before the
+ * search runs, and such a search leaves its outputs undefined without
+ * affecting later searches).
  */
 gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent,
                    int32_t *depth, void *stream);
