@@ -29,7 +29,10 @@
  *     ordinary process memory.
  *   - `stream` is a hipStream_t passed as void*; NULL means the legacy
  *     default stream.  Work is queued on it; outputs are complete once the
- *     caller synchronises that stream.
+ *     caller synchronises that stream.  The library keeps scratch per
+ *     (device, stream): calls on different streams may come from different
+ *     host threads at once; calls that share a stream should come from one
+ *     thread at a time.
  *   - Vertex IDs are int32 in [0, n); n <= 2^31 - 1.  Offsets and edge
  *     counts are int64.
  */

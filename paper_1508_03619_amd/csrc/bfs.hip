@@ -530,21 +530,25 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
     st = run_device_driven(a, p, want_stats, ws, di, stream, &levels);
     if (st != GAP_OK) return st;
   } else {
+    // the device's launch lock (held from coop_begin to coop_end) also
+    // keeps the choice of control block consistent between host threads
+    CoopOrder order;
+    st = coop_begin(g->device, stream, p.grid_split, &order);
+    if (st != GAP_OK) return st;
     used = ws->ctl + (ws->ctl_seq & 1);
     if (!ws->ctl_next_clean) GAP_HIP(hipMemsetAsync(used, 0, sizeof(Ctl), stream));
     ws->ctl_next_clean = false;  // until this search's kernel is queued
     a.ctl = used;
     a.ctl_clear = ws->ctl + ((ws->ctl_seq + 1) & 1);
-    CoopOrder order;
-    st = coop_begin(g->device, stream, p.grid_split, &order);
-    if (st != GAP_OK) return st;
     st = want_stats ? dispatch_persistent<true>(a, di, p, stream)
                     : dispatch_persistent<false>(a, di, p, stream);
+    if (st == GAP_OK) {
+      ws->ctl_seq += 1;
+      ws->ctl_next_clean = true;
+    }
     gap_status st2 = coop_end(g->device, stream, &order);
     if (st != GAP_OK) return st;
     if (st2 != GAP_OK) return st2;
-    ws->ctl_seq += 1;
-    ws->ctl_next_clean = true;
   }
   if (want_stats) {
     int done = 0, err = 0, lv = 0;
