@@ -85,6 +85,11 @@ class GraphCase:
         self.sources = inputs.pick_sources(el, nsrc, seed=src_seed)
         rp, _ = self.g.export_row_ptr()
         self.deg = np.diff(rp)
+        # m_s and reach from the raw pairs (scipy), not from any GPU output
+        rdeg, self.lab, self.comp_size, comp_edges = raw_components(el)
+        if not np.array_equal(rdeg, self.deg):
+            raise SystemExit(f"{name}: device CSR degrees differ from the raw edge list's")
+        self.ms = np.array([comp_edges[self.lab[s]] for s in self.sources], np.int64)
         self.parent = torch.empty(self.g.n, dtype=torch.int32, device="cuda")
         self.depth = torch.empty(self.g.n, dtype=torch.int32, device="cuda")
         log(f"{name}: n={self.g.n} nnz={self.g.nnz} max_deg={int(self.deg.max())} "
@@ -107,20 +112,33 @@ def committed_traffic(kernel):
     return None
 
 
-def component_edges(g, el):
-    """Per-vertex count of undirected edges in its connected component
-    (m_s of a search from that vertex), from the device CSR's degrees and
-    scipy's connected components of the raw edge list."""
+def raw_components(el):
+    """From the raw pairs alone (scipy, independent of the library): the
+    degree of every vertex in the cleaned undirected graph (distinct
+    neighbours other than itself), its connected-component label, and per
+    component the vertex count and the undirected edge count."""
     import scipy.sparse as sp
     from scipy.sparse.csgraph import connected_components
-    rp, _ = g.export_row_ptr()
-    deg = np.diff(rp)
     keep = el.src != el.dst
-    A = sp.coo_matrix((np.ones(int(keep.sum()), np.int8), (el.src[keep], el.dst[keep])),
-                      shape=(el.n, el.n)).tocsr()
-    _, lab = connected_components(A, directed=False)
-    per_comp = np.bincount(lab, weights=deg, minlength=lab.max() + 1) // 2
-    return per_comp[lab].astype(np.int64)
+    a, b = el.src[keep], el.dst[keep]
+    A = sp.coo_matrix((np.ones(2 * a.size, np.int8), (np.concatenate([a, b]), np.concatenate([b, a]))),
+                      shape=(el.n, el.n)).tocsr()  # duplicates merge: one entry per neighbour
+    deg = np.diff(A.indptr).astype(np.int64)
+    ncomp, lab = connected_components(A, directed=False)
+    size = np.bincount(lab, minlength=ncomp).astype(np.int64)
+    edges = (np.bincount(lab, weights=deg, minlength=ncomp) // 2).astype(np.int64)
+    return deg, lab, size, edges
+
+
+def component_edges(g, el):
+    """Per-vertex count of undirected edges in its connected component (m_s
+    of a search from that vertex), from the raw pairs; fails if the device
+    CSR's degrees differ from the raw graph's."""
+    deg, lab, _, edges = raw_components(el)
+    rp, _ = g.export_row_ptr()
+    if not np.array_equal(np.diff(rp), deg):
+        raise SystemExit("device CSR degrees differ from the raw edge list's")
+    return edges[lab]
 
 
 def time_launches(torch, stream, fn, reps=3):
@@ -486,6 +504,140 @@ def leg_serving(gb, torch, nq):
     return out
 
 
+def leg_strict(gb, torch, cases, stream):
+    """T_strict (every allocation for the solution inside the timed region,
+    as the paper's trial rules count it): per trial, hipMalloc of the two
+    outputs, the search, gap_shutdown (which waits and releases the
+    library's per-stream scratch, so every trial allocates it again inside
+    gap_bfs) and hipFree of the outputs, timed on the host clock.  Beside
+    it, the same sources with caller-held outputs and a resident scratch
+    pool (T_trial, the headline's convention), on the same clock."""
+    import ctypes
+    hip = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    L = gb.load()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    out = {}
+    for c in cases:
+        strict, trial = [], []
+        p = ctypes.c_void_p()
+        d = ctypes.c_void_p()
+        for s in c.sources:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if hip.hipMalloc(ctypes.byref(p), 4 * c.g.n) or hip.hipMalloc(ctypes.byref(d), 4 * c.g.n):
+                raise SystemExit("hipMalloc failed")
+            st = L.gap_bfs(c.g.handle, int(s), p, d, sh)
+            L.gap_shutdown()
+            hip.hipFree(p)
+            hip.hipFree(d)
+            strict.append(time.perf_counter() - t0)
+            if st != 0:
+                raise SystemExit(f"gap_bfs: {L.gap_last_error().decode()}")
+        for s in c.sources:
+            t0 = time.perf_counter()
+            gb.bfs(c.g, int(s), c.parent, c.depth, stream=stream)
+            stream.synchronize()
+            trial.append(time.perf_counter() - t0)
+        gb.stream_status(stream)
+        strict, trial = np.array(strict), np.array(trial)
+        out[c.name] = {"t_strict_ms_median": round(float(np.median(strict)) * 1e3, 3),
+                       "gteps_strict": round(float(c.ms.sum() / strict.sum() / 1e9), 2),
+                       "t_trial_host_ms_median": round(float(np.median(trial)) * 1e3, 3),
+                       "gteps_trial_host": round(float(c.ms.sum() / trial.sum() / 1e9), 2)}
+    log(f"T_strict: {out}")
+    return out
+
+
+def host_cpu():
+    """(threads this process may use, at most 16, and the CPU model name)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(16, max(1, n)), n, model
+
+
+def cpu_baseline_leg(gb, torch, cases, serial_seconds, stream):
+    """The CPU oracle on the host cores, and validation of every headline
+    search against it.
+
+    (i) serial: the oracle on one core over the first sources of the first
+    graph until ``serial_seconds`` have passed; (ii) source-parallel: one
+    oracle search per source for every source of every graph, on as many
+    threads as the host gives this process (at most 16), timed as a whole.
+    Then each source's GPU search (the benchmark's configuration) is checked
+    against the oracle's depths: depths bit-exact, parents valid."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    threads, nproc, model = host_cpu()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        adjs = list(ex.map(lambda c: oracle.Adjacency(c.el.n, c.el.src, c.el.dst), cases))
+    log(f"oracle adjacency for {len(cases)} graphs in {time.perf_counter() - t0:.1f}s")
+    c, A = cases[0], adjs[0]
+    done_edges, done_t, k = 0, 0.0, 0
+    for s, m in zip(c.sources, c.ms):
+        t1 = time.perf_counter()
+        A.bfs(int(s))
+        done_t += time.perf_counter() - t1
+        done_edges += int(m)
+        k += 1
+        if done_t > serial_seconds:
+            break
+    serial = {"value": round(done_edges / done_t / 1e9, 5), "unit": "GTEPS", "cores": 1,
+              "sample": f"{k} of the {len(c.sources)} {c.name} sources, {done_t:.1f}s"}
+    jobs = [(ci, int(s)) for ci, cc in enumerate(cases) for s in cc.sources]
+    t1 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        refs = list(ex.map(lambda j: adjs[j[0]].bfs(j[1])[0], jobs))
+    par_t = time.perf_counter() - t1
+    par_edges = int(sum(int(cc.ms.sum()) for cc in cases))
+    # validation: the GPU search of each source against the oracle's depths
+    ok = {cc.name: 0 for cc in cases}
+
+    def check(j, ref, p, d):
+        code, bad = adjs[j[0]].check(j[1], ref, p, d)
+        return j, code, bad
+
+    for cc in cases:
+        if cc.parent is None:
+            cc.parent = torch.empty(cc.g.n, dtype=torch.int32, device="cuda")
+            cc.depth = torch.empty(cc.g.n, dtype=torch.int32, device="cuda")
+    with ThreadPoolExecutor(threads) as ex:
+        futs = []
+        for j, ref in zip(jobs, refs):
+            cc = cases[j[0]]
+            gb.bfs(cc.g, j[1], cc.parent, cc.depth, stream=stream)
+            torch.cuda.synchronize()
+            futs.append(ex.submit(check, j, ref, cc.parent.cpu().numpy(), cc.depth.cpu().numpy()))
+        for f in futs:
+            j, code, bad = f.result()
+            if code != 0:
+                raise SystemExit(f"{cases[j[0]].name} source {j[1]}: GPU result fails the oracle "
+                                 f"check ({oracle.CHECK_NAMES.get(code, code)}, vertex {bad})")
+            ok[cases[j[0]].name] += 1
+    gb.stream_status(stream)
+    validated = {cc.name: f"{ok[cc.name]}/{len(cc.sources)}" for cc in cases}
+    log(f"validated against the oracle: {validated}")
+    return {"value": round(par_edges / par_t / 1e9, 5), "unit": "GTEPS", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"serial FIFO oracle run source-parallel on {threads} threads: all "
+                       f"{len(jobs)} sources of {'+'.join(cc.name for cc in cases)} in "
+                       f"{par_t:.1f}s wall (adjacency build untimed)"),
+            "serial_1core": serial, "host_nproc": nproc, "host_cpu": model,
+            "validated": validated}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -496,9 +648,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", default="rmat22,urand22")
-    ap.add_argument("--legs", default="serving,directed,bc,sssp,cc",
-                    help="comma list of extra legs reported in detail: serving, directed, bc, "
-                         "sssp, cc, grid4096, rmat24, mixed, or all")
+    ap.add_argument("--legs", default="strict,grid4096,rmat24,mixed,serving,directed,bc,sssp,cc",
+                    help="comma list of extra legs reported in detail: strict, serving, directed, "
+                         "bc, sssp, cc, grid4096, rmat24, mixed, or all")
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--profile-leg", action="store_true",
                     help="for rocprofv3 counter runs: a copy of known size, then one search per "
@@ -544,18 +696,20 @@ def main():
         log("profile leg done")
         return
 
-    # Per-source component edge counts m_s and per-level records (untimed).
+    # Per-level records (untimed); every search must reach exactly its
+    # source's component (sizes from the raw pairs).
     for c in cases:
-        c.ms = []
         c.alg_bytes = []
         c.levels = []
         for s in c.sources:
             recs = gb.bfs(c.g, int(s), c.parent, c.depth, stats=True)
-            d = c.depth.cpu().numpy()
-            c.ms.append(int(c.deg[d >= 0].sum()) // 2)
+            reached = int((c.depth >= 0).sum())
+            want = int(c.comp_size[c.lab[s]])
+            if reached != want:
+                raise SystemExit(f"{c.name} source {s}: the search reached {reached} vertices, "
+                                 f"its component has {want}")
             c.alg_bytes.append(algorithmic_bytes(recs, c.g.n))
             c.levels.append(len(recs))
-        c.ms = np.array(c.ms, dtype=np.int64)
         log(f"{c.name}: mean m_s={c.ms.mean():.3e} mean levels={np.mean(c.levels):.1f} "
             f"dirs(first source)={[r['direction'] for r in gb.last_stats()]}")
 
@@ -586,6 +740,7 @@ def main():
                                       for i in range(len(c.sources))])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gb.stream_status(stream)  # no timed search failed on the device
     total_edges = sum(int(c.ms.sum()) for c in cases) * args.steps
     value = total_edges / wall / 1e9
     ms_per_step = wall / args.steps * 1e3
@@ -671,7 +826,9 @@ def main():
 
     legs = set(args.legs.split(",")) if args.legs else set()
     if "all" in legs:
-        legs = {"serving", "directed", "bc", "sssp", "cc", "grid4096", "rmat24", "mixed"}
+        legs = {"strict", "serving", "directed", "bc", "sssp", "cc", "grid4096", "rmat24", "mixed"}
+    if "strict" in legs:
+        detail["strict"] = leg_strict(gb, torch, cases, stream)
     for c in cases:
         c.parent = c.depth = None
     torch.cuda.empty_cache()
@@ -694,22 +851,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        c = cases[0]
-        A = oracle.Adjacency(c.el.n, c.el.src, c.el.dst)
-        done_edges, done_t, k = 0, 0.0, 0
-        for s in c.sources:
-            t1 = time.perf_counter()
-            d, _ = A.bfs(int(s))
-            done_t += time.perf_counter() - t1
-            done_edges += int(c.deg[d >= 0].sum()) // 2
-            k += 1
-            if done_t > args.cpu_seconds:
-                break
-        cpu = {"value": round(done_edges / done_t / 1e9, 5), "unit": "GTEPS", "cores": 1,
-               "kind": "oracle",
-               "sample": f"serial FIFO oracle, {k} of the {len(c.sources)} {c.name} sources, "
-                         f"{done_t:.1f}s (adjacency build untimed)"}
+        cpu = cpu_baseline_leg(gb, torch, cases, args.cpu_seconds, stream)
+        for c in cases:
+            detail[c.name]["validated"] = cpu["validated"][c.name]
 
     out = {
         "metric": "BFS GTEPS (direction-optimizing, single-source)",

@@ -148,9 +148,10 @@ gap_status gap_graph_export_in(const gap_graph *g, int64_t *row_ptr,
  * Errors: GAP_EINVAL (NULL g or parent, source out of range),
  * GAP_ENOMEM, GAP_EDEVICE, GAP_ETIMEOUT (a device-side wait that timed
  * out: reported by gap_bfs_ex with stats and by the host-driven schedule,
- * which wait for the search; the default schedule returns before the
- * search runs, and such a search leaves its outputs undefined without
- * affecting later searches).
+ * which wait for the search).  The default schedule returns before the
+ * search runs: a search that fails on the device there leaves its outputs
+ * undefined, does not affect later searches, and records its error in the
+ * stream's sticky status word, which gap_stream_status returns.
  */
 gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent,
                    int32_t *depth, void *stream);
@@ -174,7 +175,10 @@ gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent,
  * Undirected graphs only.
  * Errors: GAP_EINVAL (NULL arrays, counts <= 0, index or source out of
  * range, graphs on different devices, a directed graph), GAP_ENOMEM,
- * GAP_EDEVICE.
+ * GAP_EDEVICE.  The call only queues the work.  A batch that fails on the
+ * device (GAP_ETIMEOUT: a bounded wait gave up; GAP_EINTERNAL) writes
+ * INT32_MIN to every entry of every lane's outputs and records the error
+ * in the stream's sticky status word (gap_stream_status).
  */
 gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          const int32_t *graph_of_source,
@@ -260,6 +264,27 @@ gap_status gap_cc(const gap_graph *g, int32_t *labels, void *stream);
  * queued on it before freeing. */
 void gap_free(gap_graph *g);
 
+/*
+ * gap_stream_status -- waits for every call queued on `stream` and returns
+ * GAP_OK, or the first error a kernel of gap_bfs, gap_bfs_batch or gap_sssp
+ * recorded on the device since the previous gap_stream_status call on that
+ * stream: GAP_ETIMEOUT (a bounded device-side wait gave up) or
+ * GAP_EINTERNAL (an inconsistent search state).  Such a failure is kept in
+ * a sticky status word of the stream's scratch, which no later search
+ * clears; this call clears it.  The default schedules queue a search and
+ * return before it runs, so this is where their device-side failures are
+ * reported.  GAP_EDEVICE for a HIP runtime error.
+ */
+gap_status gap_stream_status(void *stream);
+
+/*
+ * gap_shutdown -- waits for every device the library has used, then
+ * releases every per-stream scratch pool, event and captured graph it holds
+ * (graph handles stay valid; a later call allocates scratch again).  For
+ * process exit: the Python binding calls it at interpreter exit.
+ */
+void gap_shutdown(void);
+
 /* Message for the calling thread's most recent failure ("" if none). */
 const char *gap_last_error(void);
 
@@ -303,7 +328,13 @@ typedef struct gap_params {
   int32_t lds_bitmap;    /* persistent single-source schedule: 1 = bottom-up
                             steps copy the frontier bitmap (n/8 bytes) into
                             each workgroup's LDS when it fits, 0 = never */
-  int32_t reserved[1];
+  int32_t wait_limit_us; /* bound of one device-side wait without progress
+                            (a grid barrier, or a parked workgroup waiting
+                            for the small group), in microseconds; 0 = the
+                            built-in bounds (3 s per barrier wait, 10 s
+                            without a finished small level).  A wait that
+                            gives up ends the search with GAP_ETIMEOUT; every
+                            kernel still exits. */
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

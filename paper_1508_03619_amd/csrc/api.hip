@@ -1,6 +1,7 @@
 // C ABI of libgapbfs and its host runtime: errors, device facts, per-stream
 // workspaces, the parameter set.
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -232,6 +233,10 @@ gap_status params_check(const gap_params &p) {
     set_error("params: small_frontier must be >= 0");
     return GAP_EINVAL;
   }
+  if (p.wait_limit_us < 0) {
+    set_error("params: wait_limit_us must be >= 0");
+    return GAP_EINVAL;
+  }
   if (p.batch_alpha < 1 || p.batch_beta < 1) {
     set_error("params: batch_alpha and batch_beta must be >= 1");
     return GAP_EINVAL;
@@ -252,6 +257,15 @@ Workspace *workspace_for(int dev, hipStream_t stream) {
   if (!ws) return nullptr;
   ws->device = dev;
   ws->stream = stream;
+  if (hipMalloc(&ws->sticky, 256) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (hipMemsetAsync(ws->sticky, 0, 256, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(ws->sticky);
+    return nullptr;
+  }
   Workspace *raw = ws.get();
   g_ws.emplace(key, std::move(ws));
   return raw;
@@ -397,6 +411,69 @@ gap_status workspace_reserve_cc(Workspace *ws, size_t bytes) {
     ws->cc_bytes = bytes;
   }
   return GAP_OK;
+}
+
+gap_status stream_status(hipStream_t stream) {
+  std::vector<Workspace *> wss;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_ws)
+      if (kv.first.second == stream) wss.push_back(kv.second.get());
+  }
+  gap_status first = GAP_OK;
+  for (Workspace *ws : wss) {
+    GAP_HIP(hipSetDevice(ws->device));
+    GAP_HIP(hipStreamSynchronize(stream));
+    int code = 0;
+    GAP_HIP(hipMemcpy(&code, ws->sticky, sizeof(int), hipMemcpyDeviceToHost));
+    if (code != 0) {
+      GAP_HIP(hipMemsetAsync(ws->sticky, 0, sizeof(int), stream));
+      GAP_HIP(hipStreamSynchronize(stream));
+      if (first == GAP_OK) first = code;
+    }
+  }
+  if (first != GAP_OK)
+    set_error("a search queued on this stream failed on the device (%s); its outputs are undefined",
+              first == GAP_ETIMEOUT ? "a bounded wait gave up" : "inconsistent state");
+  return first;
+}
+
+static void release_workspace(Workspace *ws) {
+  (void)hipSetDevice(ws->device);
+  release_single(ws);
+  free_dev(ws->recs);
+  ws->cap_recs = 0;
+  if (ws->ms_buf) (void)hipFree(ws->ms_buf);
+  if (ws->ms_host) (void)hipHostFree(ws->ms_host);
+  if (ws->bc_buf) (void)hipFree(ws->bc_buf);
+  if (ws->bc_lv) (void)hipFree(ws->bc_lv);
+  if (ws->bc_host) (void)hipHostFree(ws->bc_host);
+  if (ws->bc_event) (void)hipEventDestroy(ws->bc_event);
+  if (ws->sp_buf) (void)hipFree(ws->sp_buf);
+  if (ws->sp_host) (void)hipHostFree(ws->sp_host);
+  if (ws->cc_buf) (void)hipFree(ws->cc_buf);
+  free_dev(ws->sticky);
+}
+
+void release_all() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::vector<int> devs;
+  for (auto &kv : g_ws) devs.push_back(kv.first.first);
+  for (auto &kv : g_coop) devs.push_back(kv.first);
+  std::sort(devs.begin(), devs.end());
+  devs.erase(std::unique(devs.begin(), devs.end()), devs.end());
+  for (int d : devs) {
+    (void)hipSetDevice(d);
+    (void)hipDeviceSynchronize();
+  }
+  for (auto &kv : g_ws) release_workspace(kv.second.get());
+  g_ws.clear();
+  for (auto &kv : g_coop) {
+    (void)hipSetDevice(kv.first);
+    for (hipEvent_t e : kv.second->ev) (void)hipEventDestroy(e);
+  }
+  g_coop.clear();
+  (void)hipGetLastError();
 }
 
 }  // namespace gap
@@ -726,6 +803,13 @@ gap_status gap_cc(const gap_graph *g, int32_t *labels, void *stream) {
   GAP_HIP(hipSetDevice(g->device));
   return run_cc(g, labels, (hipStream_t)stream);
 }
+
+gap_status gap_stream_status(void *stream) {
+  clear_error();
+  return stream_status((hipStream_t)stream);
+}
+
+void gap_shutdown(void) { release_all(); }
 
 gap_status gap_stream_copy(void *dst, const void *src, int64_t bytes, void *stream) {
   clear_error();

@@ -24,6 +24,7 @@ struct SearchArgs {
   uint64_t *vbm;
   Ctl *ctl;
   Ctl *ctl_clear;  // persistent kernel: the next search's control block, cleared at start
+  int *sticky;     // the stream's sticky status word (persistent kernel)
   Params p;
   DevLevelRec *recs;
   int32_t max_recs;
@@ -77,7 +78,7 @@ struct SmallDecision {
 };
 
 template <int BLOCK, bool STATS>
-__global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
+__device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
   __shared__ Stage<BLOCK> st;
   extern __shared__ uint64_t lds_fbm[];  // frontier bitmap copy (lds_bm)
   const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   }
   Totals part = {};
   if (tid == 0) part = init_source(a.g, a.Q, a.ctl, a.source, a.p.hub, a.p.chunk);
-  if (!grid_sync(a.ctl, nblocks, part, 0, 0)) return;
+  if (!grid_sync(a.ctl, nblocks, part, 0, 0, a.p.wait)) return;
 
   int32_t d = 0, dir = kTopDown;
   bool have_bm = false;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     const int32_t ndir = decide_direction(dir, nv, mf, mu, nf_prev, a.g.n, a.p, d);
     if (ndir == kBottomUp && !(dir == kBottomUp && have_bm)) {
       convert_to_bitmaps(a.g, a.parent, a.depth, d, (fsel ? a.bm1 : a.bm0), a.vbm, gwave, nwaves);
-      if (!grid_sync(a.ctl, nblocks, Totals{}, -1, 0)) return;
+      if (!grid_sync(a.ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
       have_bm = true;
     }
     if (dir == kBottomUp && ndir == kTopDown) {
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
       queue_from_bitmap<BLOCK>(c, st, (fsel ? a.bm1 : a.bm0), gwave,
                                small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
       int unused = 0;
-      if (!grid_sync_x(a.ctl, small ? small_barrier(a.ctl) : main_barrier(a.ctl),
+      if (!grid_sync_x(a.ctl, small ? small_barrier(a.ctl, a.p.wait) : main_barrier(a.ctl, a.p.wait),
                        small ? nsmall : nblocks, Totals{}, d & 1, d & 1, NoDecision{}, unused))
         return;
     }
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     const SmallDecision dec{a.g.n, mu, nv, (int64_t)a.p.small, dir, d, have_bm ? 1 : 0, fsel_next,
                             a.p, small, small_enabled};
     int small_next = 0;
-    const BarrierSet bar = small ? small_barrier(a.ctl) : main_barrier(a.ctl);
+    const BarrierSet bar = small ? small_barrier(a.ctl, a.p.wait) : main_barrier(a.ctl, a.p.wait);
     if (!grid_sync_x(a.ctl, bar, small ? nsmall : nblocks, t, (d + 1) & 1, (d + 1) & 1, dec,
                      small_next))
       return;
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
     if (small_next && !small && blockIdx.x >= nsmall) {
       // park until the small group hands the search back
       ParkState ps;
-      if (!park_wait(a.ctl, (unsigned int)d, ps)) return;
+      if (!park_wait(a.ctl, (unsigned int)d, ps, a.p.wait_park)) return;
       d = uni(ps.level);
       dir = uni(ps.dir);
       have_bm = uni(ps.have_bm) != 0;
@@ -187,6 +188,12 @@ __global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
   }
   fixup_parents(a.g.n, a.parent, tid, nthreads);
   if (tid == 0) a.ctl->levels = d;
+}
+
+template <int BLOCK, bool STATS>
+__global__ __launch_bounds__(BLOCK) void k_bfs_persistent(SearchArgs a) {
+  bfs_persistent<BLOCK, STATS>(a);
+  note_error(a.sticky, a.ctl);
 }
 
 // ---- device-driven per-level kernels (levels and graph schedules) -------------
@@ -517,7 +524,9 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
   a.bm1 = ws->bm[1];
   a.vbm = ws->bm[2];
   a.ctl = ws->ctl;
-  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier};
+  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier, 0, 0};
+  set_wait_limits(a.p, p.wait_limit_us);
+  a.sticky = ws->sticky;
   a.recs = want_stats ? ws->recs : nullptr;
   a.max_recs = want_stats ? max_levels : 0;
 

@@ -102,7 +102,12 @@ struct Ctl {
 struct Params {
   int32_t alpha, beta, direction, hub, chunk;
   int32_t small;  // top-down levels with |F| and m_f at most this run on the small group
+  uint64_t wait;       // bound of one barrier wait (real-time ticks)
+  uint64_t wait_park;  // bound of a parked workgroup's wait without progress
 };
+
+// Device-side wait bounds from gap_params::wait_limit_us (0: the defaults).
+inline void set_wait_limits(Params &p, int32_t wait_limit_us);
 
 enum Dir : int32_t { kTopDown = 1, kBottomUp = 2 };
 
@@ -174,6 +179,7 @@ __device__ inline int64_t uni(int64_t x) {
 __device__ inline uint64_t rt_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
 constexpr uint64_t kBarrierTimeoutTicks = 300000000ull;  // ~3 s at 100 MHz
+constexpr uint64_t kTicksPerUs = 100ull;
 
 __device__ inline unsigned long long ld_agent(const unsigned long long *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -237,13 +243,19 @@ __device__ inline Totals take_totals(GroupSlot &s) {
 
 // The counters and flags of one barrier: the whole grid's or the small
 // group's.
+// `limit` bounds one wait for the release, in real-time ticks.
 struct BarrierSet {
   GroupSlot *grp;
   GroupSlot *top;
   GenFlag *gen;
+  uint64_t limit;
 };
-__device__ inline BarrierSet main_barrier(Ctl *c) { return {c->grp, &c->top, c->gen}; }
-__device__ inline BarrierSet small_barrier(Ctl *c) { return {c->sgrp, &c->stop, c->sgen}; }
+__device__ inline BarrierSet main_barrier(Ctl *c, uint64_t limit = kBarrierTimeoutTicks) {
+  return {c->grp, &c->top, c->gen, limit};
+}
+__device__ inline BarrierSet small_barrier(Ctl *c, uint64_t limit = kBarrierTimeoutTicks) {
+  return {c->sgrp, &c->stop, c->sgen, limit};
+}
 
 // What the last arriver decides for everyone: a flag delivered with the
 // release (bit 0 of the generation word) and, when resume >= 0, a value
@@ -267,8 +279,8 @@ struct NoDecision {
 // (a release store per flag would write the L2 back once per flag).  The
 // generation word advances by 2 and carries the decision's flag in bit 0;
 // `flag` returns it to every participant.
-// Bounded: a workgroup that waits longer than the timeout records
-// GAP_ETIMEOUT in ctl->err.  Returns false once an error has been recorded.
+// Bounded: a workgroup that waits longer than B.limit records GAP_ETIMEOUT
+// in ctl->err.  Returns false once an error has been recorded.
 template <class Decide>
 __device__ inline bool grid_sync_x(Ctl *ctl, BarrierSet B, unsigned int nblocks, const Totals &part,
                                    int publish, int bs, const Decide &decide, int &flag) {
@@ -315,7 +327,7 @@ __device__ inline bool grid_sync_x(Ctl *ctl, BarrierSet B, unsigned int nblocks,
       unsigned int v;
       while ((v = ld_agent(&B.gen[g].gen)) == gen0) {
         __builtin_amdgcn_s_sleep(1);
-        if (rt_clock() - t0 > kBarrierTimeoutTicks) {
+        if (rt_clock() - t0 > B.limit) {
           __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
@@ -335,26 +347,39 @@ __device__ inline bool grid_sync_x(Ctl *ctl, BarrierSet B, unsigned int nblocks,
 }
 
 __device__ inline bool grid_sync(Ctl *ctl, unsigned int nblocks, const Totals &part, int publish,
-                                 int bs) {
+                                 int bs, uint64_t limit = kBarrierTimeoutTicks) {
   int flag;
-  return grid_sync_x(ctl, main_barrier(ctl), nblocks, part, publish, bs, NoDecision{}, flag);
+  return grid_sync_x(ctl, main_barrier(ctl, limit), nblocks, part, publish, bs, NoDecision{}, flag);
 }
 
 // A parked workgroup waits until the small group sets ctl->resume above
-// `level` (bounded like the barrier), then takes over the handed-on state.
-constexpr uint64_t kParkTimeoutTicks = 3000000000ull;  // ~30 s at 100 MHz
+// `level`, then takes over the handed-on state.  The wait is bounded by the
+// time without progress, not by its total length: every release of the
+// small group's barrier (one per small level) restarts the clock, so a
+// search of millions of small levels in a row never trips it, while a small
+// group that stops making progress is caught after `limit` ticks.
+constexpr uint64_t kParkTimeoutTicks = 1000000000ull;  // ~10 s at 100 MHz
 
-__device__ inline bool park_wait(Ctl *ctl, unsigned int level, ParkState &ps) {
+__device__ inline bool park_wait(Ctl *ctl, unsigned int level, ParkState &ps, uint64_t limit) {
   __syncthreads();
   __shared__ int s_ok;
   __shared__ ParkState s_ps;
   if (threadIdx.x == 0) {
     int ok = 1;
-    const uint64_t t0 = rt_clock();
+    uint64_t t0 = rt_clock();
+    unsigned int seen = ld_agent(&ctl->sgen[0].gen);
     while (ld_agent(&ctl->resume) <= level) {
       __builtin_amdgcn_s_sleep(32);
-      if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-          rt_clock() - t0 > kParkTimeoutTicks) {
+      if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        break;
+      }
+      const unsigned int g = ld_agent(&ctl->sgen[0].gen);
+      const uint64_t now = rt_clock();
+      if (g != seen) {  // the small group finished another level
+        seen = g;
+        t0 = now;
+      } else if (now - t0 > limit) {
         __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
@@ -369,6 +394,22 @@ __device__ inline bool park_wait(Ctl *ctl, unsigned int level, ParkState &ps) {
   __syncthreads();
   ps = s_ps;
   return s_ok != 0;
+}
+
+inline void set_wait_limits(Params &p, int32_t wait_limit_us) {
+  p.wait = wait_limit_us > 0 ? (uint64_t)wait_limit_us * kTicksPerUs : kBarrierTimeoutTicks;
+  p.wait_park = wait_limit_us > 0 ? (uint64_t)wait_limit_us * kTicksPerUs : kParkTimeoutTicks;
+}
+
+// End of a kernel that may have recorded an error in ctl->err: thread 0 of
+// every workgroup copies it to the stream's sticky status word, which the
+// next search does not clear (the host reads and clears it).  The workgroup
+// that recorded the error always sees its own store, so a failure is never
+// lost when the control block is cleared for a later search.
+__device__ inline void note_error(int *sticky, const Ctl *ctl) {
+  if (threadIdx.x != 0 || !sticky) return;
+  const int e = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (e != 0) atomicCAS(sticky, 0, e);
 }
 
 }  // namespace gap

@@ -82,6 +82,7 @@ struct MsArgs {
   int32_t nlanes;
   Queues Q;                 // virtual vertex IDs
   MsCtl *ctl;
+  int *sticky;              // the stream's sticky status word
   Params p;
 };
 
@@ -166,7 +167,7 @@ __device__ inline uint64_t wave_excl_or_u64(uint64_t x) {
 // ---- the persistent kernel ---------------------------------------------------------
 
 template <int W>
-__global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
+__device__ __forceinline__ void msbfs(const MsArgs &a) {
   __shared__ MsShared<W> sh;
   const int64_t nthreads = (int64_t)gridDim.x * kMsBlock;
   const int64_t tid = (int64_t)blockIdx.x * kMsBlock + threadIdx.x;
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
     a.V[i] = 0ull;
     F[i] = 0ull;
   }
-  if (!grid_sync(ctl, nblocks, Totals{}, -1, 0)) return;
+  if (!grid_sync(ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
   for (int64_t l = tid; l < a.nlanes; l += nthreads) {
     int s = 0;  // lane -> segment (few segments: linear)
     while (s + 1 < nseg && sh.lane_base[s + 1] <= l) ++s;
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
     a.P[tile_index<W>(vv, li / 64, li % 64)] = src;
     a.D[tile_index<W>(vv, li / 64, li % 64)] = 0;
   }
-  if (!grid_sync(ctl, nblocks, Totals{}, -1, 0)) return;
+  if (!grid_sync(ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
 
   const int64_t nwords = a.nvirt / kWave;
   const bool tracer = blockIdx.x == 0 && threadIdx.x == 0;
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
       for (int w = 0; w < W; ++w)
         if (sh.acc_or[s][w]) atomicOr(&T.lanes_or[w], sh.acc_or[s][w]);
     }
-    if (!grid_sync(ctl, nblocks, Totals{}, (d + 1) & 1, (d + 1) & 1)) return;
+    if (!grid_sync(ctl, nblocks, Totals{}, (d + 1) & 1, (d + 1) & 1, a.p.wait)) return;
 
     // ---- decide per segment -----------------------------------------------------
     if (threadIdx.x == 0) sh.nlive = 0;
@@ -535,16 +536,25 @@ __global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
         }
       }
     }
-    if (!grid_sync(ctl, nblocks, Totals{}, -1, 0)) return;
+    if (!grid_sync(ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
     if (tracer && d < kMsTraceLevels) a.ctl->trace[d][2] = rt_clock();
     swap_ptr(F, N);
   }
 }
 
+template <int W>
+__global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
+  msbfs<W>(a);
+  note_error(a.sticky, &a.ctl->base);
+}
+
 // ---- output: scratch tiles -> per-lane arrays ------------------------------------------
 // A wave takes one 64-vertex word and copies each lane's 64 slots to that
 // lane's output (coalesced 256-byte reads and writes), writing -1 where the
-// lane never reached the vertex.
+// lane never reached the vertex.  When the search kernel recorded an error
+// (a timed-out wait, an inconsistent state), every output entry becomes
+// INT32_MIN instead, so a failed batch can never pass for one whose lanes
+// reached nothing.
 
 constexpr int kOutBlock = 256;
 
@@ -555,6 +565,8 @@ __global__ __launch_bounds__(kOutBlock) void k_ms_output(MsArgs a, int64_t nword
   const int nseg = a.nseg;
   for (int s = threadIdx.x; s <= nseg; s += kOutBlock) s_base[s] = tile_base[s];
   __syncthreads();
+  const bool failed = __hip_atomic_load(&a.ctl->base.err, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) != 0;
   const int lane = lane_id();
   const int64_t nwaves = (int64_t)gridDim.x * kOutBlock / kWave;
   const int64_t gwave = ((int64_t)blockIdx.x * kOutBlock + threadIdx.x) / kWave;
@@ -571,9 +583,9 @@ __global__ __launch_bounds__(kOutBlock) void k_ms_output(MsArgs a, int64_t nword
         const int l = sg.lane_base + w * 64 + i;
         const int64_t t = tile_index<W>(vv0 + lane, w, i);
         const bool hit = ((vis >> i) & 1ull) != 0ull;
-        if (real) a.parents[l][vl0 + lane] = hit ? a.P[t] : -1;
+        if (real) a.parents[l][vl0 + lane] = failed ? INT32_MIN : (hit ? a.P[t] : -1);
         int32_t *dp = a.depths[l];
-        if (dp && real) dp[vl0 + lane] = hit ? a.D[t] : -1;
+        if (dp && real) dp[vl0 + lane] = failed ? INT32_MIN : (hit ? a.D[t] : -1);
       }
     }
   }
@@ -735,7 +747,9 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
   a.ctl = reinterpret_cast<MsCtl *>(base + o_ctl);
   // bottom-up cannot stop early while any lane still misses a vertex, so the
   // batch has its own switching thresholds
-  a.p = Params{p.batch_alpha, p.batch_beta, p.direction, p.hub_degree, p.chunk_edges, 0};
+  a.p = Params{p.batch_alpha, p.batch_beta, p.direction, p.hub_degree, p.chunk_edges, 0, 0, 0};
+  set_wait_limits(a.p, p.wait_limit_us);
+  a.sticky = ws->sticky;
   const int64_t *d_tile_base = reinterpret_cast<const int64_t *>(base + o_tb);
 
   CoopOrder order;

@@ -68,6 +68,11 @@ struct DevLevelRec {
 struct Workspace {
   int device = -1;
   hipStream_t stream = nullptr;
+  // Sticky status of the searches queued on this stream: a kernel that
+  // records an error (a timed-out wait, an inconsistent state) also stores
+  // it here, where no later search clears it; gap_stream_status reads and
+  // clears it.  Device int, allocated with the workspace.
+  int *sticky = nullptr;
   // single source
   int64_t cap_n = 0;
   int64_t cap_chunks = 0;
@@ -110,7 +115,15 @@ struct Workspace {
   void *cc_buf = nullptr;
 };
 
+// The workspace of (dev, stream), created on first use (NULL when its
+// allocation fails).  The caller has made `dev` current.
 Workspace *workspace_for(int dev, hipStream_t stream);
+// Waits for `stream` and returns (and clears) the first error a kernel
+// recorded in the sticky status word of any of its workspaces.
+gap_status stream_status(hipStream_t stream);
+// Waits for every device the library used and releases every workspace,
+// event and captured graph it holds.
+void release_all();
 gap_status workspace_reserve_single(Workspace *ws, int64_t n, int64_t nnz, const gap_params &p);
 gap_status workspace_reserve_recs(Workspace *ws, int32_t nrec);
 gap_status workspace_reserve_ms(Workspace *ws, size_t bytes, size_t host_bytes);

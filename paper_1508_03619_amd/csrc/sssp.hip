@@ -87,6 +87,7 @@ struct SpArgs {
   int32_t *far[2];
   SpCtl *sc;
   Ctl *ctl;
+  int *sticky;  // the stream's sticky status word
   int32_t source;
   uint32_t delta;
 };
@@ -251,7 +252,7 @@ struct SpDecide {
   }
 };
 
-__global__ __launch_bounds__(kSpBlock) void k_sssp(SpArgs a) {
+__device__ __forceinline__ void sssp_body(const SpArgs &a) {
   const unsigned int nblocks = gridDim.x;
   const int64_t tid = blockIdx.x * (int64_t)kSpBlock + threadIdx.x;
   const int64_t nthreads = (int64_t)nblocks * kSpBlock;
@@ -377,6 +378,11 @@ __global__ __launch_bounds__(kSpBlock) void k_sssp(SpArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kSpBlock) void k_sssp(SpArgs a) {
+  sssp_body(a);
+  note_error(a.sticky, a.ctl);
+}
+
 // Control state before a search: the first barrier's bookkeeping treats
 // the source's items (near queue 1) like the output of a compaction into
 // the first bucket [0, delta).
@@ -432,6 +438,7 @@ gap_status run_sssp(const gap_graph *g, int32_t source, uint32_t *dist, uint32_t
   a.far[1] = carve<int32_t>(p, n);
   a.sc = carve<SpCtl>(p, 1);
   a.ctl = carve<Ctl>(p, 1);
+  a.sticky = ws->sticky;
   a.source = source;
   a.delta = delta;
   k_sp_init<<<1, 1, 0, stream>>>(a.sc, delta);

@@ -7,6 +7,7 @@ library is not built, every call raises: there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
@@ -38,10 +39,10 @@ class _Params(ctypes.Structure):
                 ("graph_chunk", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
                 ("batch_alpha", ctypes.c_int32), ("batch_beta", ctypes.c_int32),
                 ("grid_split", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
-                ("lds_bitmap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("lds_bitmap", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32)]
 
 
-PARAM_NAMES = [f[0] for f in _Params._fields_ if f[0] != "reserved"]
+PARAM_NAMES = [f[0] for f in _Params._fields_]
 
 
 class LevelStat(ctypes.Structure):
@@ -62,7 +63,8 @@ EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_
             "gap_graph_export_in", "gap_bfs", "gap_bfs_batch",
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
             "gap_device_query", "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
-            "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc"]
+            "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc", "gap_stream_status",
+            "gap_shutdown"]
 
 
 def library_path() -> str:
@@ -111,13 +113,20 @@ def load():
         L.gap_sssp.argtypes = [vp, i32, vp, ctypes.c_uint32, vp]
         L.gap_sssp_ex.argtypes = [vp, i32, vp, ctypes.c_uint32, vp, i32p]
         L.gap_cc.argtypes = [vp, vp, vp]
+        L.gap_stream_status.argtypes = [vp]
+        L.gap_shutdown.argtypes = []
+        L.gap_shutdown.restype = None
         for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_graph_export_in",
                      "gap_graph_directed", "gap_bfs", "gap_bfs_ex",
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
                      "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
-                     "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc"):
+                     "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc",
+                     "gap_stream_status"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
+        # release the library's scratch, events and captured graphs before
+        # the HIP runtime and any attached profiler tear down
+        atexit.register(L.gap_shutdown)
         _apply_tuned(L)
         return L
 
@@ -410,6 +419,18 @@ def cc(g: Graph, labels, stream=None):
     if labels.numel() < g.n:
         raise ValueError("labels shorter than n")
     _check(L.gap_cc(g.handle, _ptr(labels), _stream_handle(stream)))
+
+
+def stream_status(stream=None):
+    """Wait for ``stream`` and raise GapError if a search queued on it failed
+    on the device since the last check (gap_stream_status)."""
+    _check(load().gap_stream_status(_stream_handle(stream)))
+
+
+def shutdown():
+    """Release the library's per-stream scratch, events and captured graphs
+    (gap_shutdown); later calls allocate them again."""
+    load().gap_shutdown()
 
 
 def device_query() -> dict:

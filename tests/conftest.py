@@ -29,3 +29,17 @@ def gpu():
     import paper_1508_03619_amd as gb
     gb.load()
     return gb
+
+
+@pytest.fixture(autouse=True)
+def _device_status(request):
+    """After every GPU test: no search queued on the current stream may have
+    failed on the device unnoticed (gap_stream_status)."""
+    yield
+    if request.node.get_closest_marker("gpu") is None:
+        return
+    import torch
+    if not torch.cuda.is_available():
+        return
+    from paper_1508_03619_amd import gapbfs
+    gapbfs.stream_status()

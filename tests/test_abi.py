@@ -81,7 +81,19 @@ def test_params_validation(lib):
         gapbfs.set_params(chunk_edges=100)
     with pytest.raises(gapbfs.GapError):
         gapbfs.set_params(alpha=0)
+    with pytest.raises(gapbfs.GapError):
+        gapbfs.set_params(wait_limit_us=-1)
     assert gapbfs.get_params() == p
+    assert p["wait_limit_us"] == 0  # built-in device-side wait bounds
+
+
+def test_status_and_shutdown_without_work(lib):
+    """A stream with no queued search has nothing to report; shutdown with
+    nothing allocated is a no-op."""
+    from paper_1508_03619_amd import gapbfs
+    assert lib.gap_stream_status(None) == gapbfs.GAP_OK
+    lib.gap_shutdown()
+    assert lib.gap_stream_status(None) == gapbfs.GAP_OK
 
 
 def test_no_device_reports_edevice(lib):

@@ -7,16 +7,19 @@ directed graph, betweenness centrality on R-MAT scale 22, shortest paths
 on R-MAT and uniform scale 22 with weights 1..255, and connected components
 at scale 22.
 
-Sampled searches are checked in full against the oracle (depths bit-exact,
-parents valid, Section 2.1).  Every lane of a large batch is also checked
-for properties that hold at any size: parent[s] = s, depth[s] = 0, and the
-reached set has the size of the source's connected component, computed by
-the oracle's union-find."""
+Checked in full against the oracle (depths bit-exact, parents valid,
+Section 2.1): all 64 benchmark sources of R-MAT 22 and uniform 2^22 as
+single searches and every lane of their 64-lane batches; every lane of the
+R-MAT 24 64-lane batch and 16 lanes of the 256-lane batch; 4 grid sources
+in both schedules; every lane of the mixed batches.  Every lane of every
+batch is also checked on the device against properties that hold at any
+size: parent[s] = s, depth[s] = 0, and the reached set is exactly the
+source's connected component from the oracle's union-find."""
 import numpy as np
 import pytest
 
 import oracle
-from tests.gpuutil import assert_valid, say
+from tests.gpuutil import assert_valid, check_all, say
 
 pytestmark = pytest.mark.gpu
 
@@ -45,12 +48,11 @@ def adjacency(name):
     return w["A"]
 
 
-def comp_sizes(name):
+def comp_labels(name):
     w = workload(name)
     if w["cc"] is None:
         say(f"{name}: oracle components")
-        lab = oracle.components(w["el"].n, w["el"].src, w["el"].dst)
-        w["cc"] = (lab, np.bincount(lab, minlength=w["el"].n))
+        w["cc"] = oracle.components(w["el"].n, w["el"].src, w["el"].dst)
     return w["cc"]
 
 
@@ -65,72 +67,92 @@ def bench_sources(name, k=64):
     return [int(x) for x in inputs.pick_sources(workload(name)["el"], k, seed=inputs.SOURCE_SEEDS[name])]
 
 
-def run_single(g, s, params=None):
+def run_single(g, s, params=None, p=None, d=None):
     import torch
     from paper_1508_03619_amd import gapbfs as gb
-    p = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    p = torch.empty(g.n, dtype=torch.int32, device="cuda") if p is None else p
+    d = torch.empty(g.n, dtype=torch.int32, device="cuda") if d is None else d
     gb.bfs(g, s, p, d, params=params)
     torch.cuda.synchronize()
+    gb.stream_status()
     return p.cpu().numpy(), d.cpu().numpy()
 
 
-def check_batch_properties(name, lanes, P, D):
-    """Every lane: source entries and reached-set size (on the device)."""
+def check_batch_properties(what, labels, lanes, P, D):
+    """Every lane, on the device: source entries, and the reached set equals
+    the source's component (oracle union-find labels, uploaded once)."""
     import torch
-    lab, size = comp_sizes(name)
+    lab_t = torch.from_numpy(np.ascontiguousarray(labels)).to("cuda")
     for i, s in enumerate(lanes):
-        assert int(P[i][s]) == s and int(D[i][s]) == 0, f"{name} lane {i}: source entries"
-        reached = int((D[i] >= 0).sum())
-        assert reached == int(size[lab[s]]), f"{name} lane {i}: reached {reached} != component {size[lab[s]]}"
-        assert int((P[i] >= 0).sum()) == reached, f"{name} lane {i}: parent/depth reach differ"
+        assert int(P[i][s]) == s and int(D[i][s]) == 0, f"{what} lane {i}: source entries"
+        reached = D[i] >= 0
+        comp = lab_t == int(labels[s])
+        assert torch.equal(reached, comp), \
+            f"{what} lane {i}: reached {int(reached.sum())} vertices, component has {int(comp.sum())}"
+        assert torch.equal(P[i] >= 0, reached), f"{what} lane {i}: parent/depth reach differ"
         assert int(P[i].min()) >= -1 and int(D[i].min()) >= -1
+    del lab_t
 
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", ["rmat22", "urand22"])
 def test_fullsize_single_and_batch(gpu, name):
+    """All 64 benchmark sources: the single search and the batch lane of
+    each, in full against one oracle search per source."""
     import torch
     from paper_1508_03619_amd import gapbfs as gb
     srcs = bench_sources(name)
     g = workload(name)["g"]
     A = adjacency(name)
-    for i in (0, 37):
-        say(f"{name}: single-source search {i} (source {srcs[i]}) vs oracle")
-        p, d = run_single(g, srcs[i])
-        assert_valid(A, srcs[i], p, d, what=name)
     say(f"{name}: 64-lane batch")
     P = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
     D = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
     gb.bfs_batch([g], [0] * 64, srcs, P, D)
     torch.cuda.synchronize()
-    check_batch_properties(name, srcs, P, D)
-    for i in (5, 63):
-        say(f"{name}: batch lane {i} vs oracle")
-        assert_valid(A, srcs[i], P[i].cpu().numpy(), D[i].cpu().numpy(), what=f"{name} lane {i}")
+    gb.stream_status()
+    check_batch_properties(name, comp_labels(name), srcs, P, D)
+    p1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    d1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def items():
+        for i, s in enumerate(srcs):
+            p, d = run_single(g, s, p=p1, d=d1)
+            yield A, s, [(f"single {i}", p, d), (f"lane {i}", P[i].cpu().numpy(), D[i].cpu().numpy())]
+
+    say(f"{name}: 64 single searches and 64 lanes vs the oracle")
+    assert check_all(items(), what=name) == 128
     del P, D
     drop(name)
 
 
 @pytest.mark.timeout(900)
 def test_fullsize_grid4096_persistent_and_graph(gpu):
+    """Four benchmark sources of the road-like grid, each in the persistent
+    kernel and in captured level graphs."""
     name = "grid4096"
-    srcs = bench_sources(name, 2)
+    srcs = bench_sources(name, 4)
     g = workload(name)["g"]
     A = adjacency(name)
-    s = srcs[0]
-    ref = A.bfs(s)[0]
-    say(f"grid4096: source {s}, {int(ref.max())} levels")
-    for mode in (0, 2):
-        say(f"grid4096: mode {mode}")
-        p, d = run_single(g, s, params={"mode": mode})
-        assert_valid(A, s, p, d, ref, what=f"grid4096 mode {mode}")
+
+    def items():
+        for s in srcs:
+            res = []
+            for mode in (0, 2):
+                say(f"grid4096: source {s} mode {mode}")
+                p, d = run_single(g, s, params={"mode": mode})
+                res.append((f"mode {mode}", p, d))
+            yield A, s, res
+
+    assert check_all(items(), what="grid4096") == 8
     drop(name)
 
 
 @pytest.mark.timeout(1200)
 @pytest.mark.parametrize("lanes", [64, 256])
 def test_fullsize_rmat24_batch(gpu, lanes):
+    """Every lane against the source's component on the device; all 64
+    lanes of the 64-lane batch and 16 spread lanes of the 256-lane batch in
+    full against the oracle."""
     import torch
     from paper_1508_03619_amd import gapbfs as gb
     name = "rmat24"
@@ -141,12 +163,14 @@ def test_fullsize_rmat24_batch(gpu, lanes):
     D = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
     gb.bfs_batch([g], [0] * lanes, srcs, P, D)
     torch.cuda.synchronize()
+    gb.stream_status()
     say(f"rmat24: properties of {lanes} lanes")
-    check_batch_properties(name, srcs, P, D)
+    check_batch_properties(name, comp_labels(name), srcs, P, D)
     A = adjacency(name)
-    for i in (0, lanes - 1):
-        say(f"rmat24: lane {i} vs oracle")
-        assert_valid(A, srcs[i], P[i].cpu().numpy(), D[i].cpu().numpy(), what=f"rmat24 lane {i}")
+    full = list(range(lanes)) if lanes == 64 else list(range(0, lanes, lanes // 16))
+    say(f"rmat24: {len(full)} lanes vs the oracle")
+    items = ((A, srcs[i], [(f"lane {i}", P[i].cpu().numpy(), D[i].cpu().numpy())]) for i in full)
+    assert check_all(items, what=f"rmat24 batch {lanes}") == len(full)
     del P, D
     torch.cuda.empty_cache()
     if lanes == 256:
@@ -159,6 +183,9 @@ MIXED_SCALES = [14, 14, 15, 15, 16, 16, 17, 17, 18, 18, 19, 19, 20, 20, 20, 20]
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("per_graph", [4, 16])
 def test_fullsize_mixed_batch(gpu, per_graph):
+    """16 R-MAT graphs of scales 14-20 in one launch: every lane in full
+    against the oracle of its own graph, and its reached set against that
+    graph's components."""
     import torch
     from paper_1508_03619_amd import inputs, gapbfs as gb
     els = [inputs.rmat(s, 16, seed=30000 + i) for i, s in enumerate(MIXED_SCALES)]
@@ -173,29 +200,26 @@ def test_fullsize_mixed_batch(gpu, per_graph):
     D = [torch.empty(graphs[gi].n, dtype=torch.int32, device="cuda") for gi in gos]
     gb.bfs_batch(graphs, gos, srcs, P, D)
     torch.cuda.synchronize()
-    done = set()
-    for i, (gi, s) in enumerate(zip(gos, srcs)):
-        if gi in done:
-            continue  # one lane per graph in full against the oracle
-        done.add(gi)
-        A = oracle.Adjacency(els[gi].n, els[gi].src, els[gi].dst)
-        assert_valid(A, s, P[i].cpu().numpy(), D[i].cpu().numpy(), what=f"mixed graph {gi} lane {i}")
+    gb.stream_status()
+    As = [oracle.Adjacency(e.n, e.src, e.dst) for e in els]
     for gi, e in enumerate(els):
-        lab = oracle.components(e.n, e.src, e.dst)
-        size = np.bincount(lab, minlength=e.n)
-        for i in [k for k in range(len(gos)) if gos[k] == gi]:
-            s = srcs[i]
-            assert int(D[i][s]) == 0 and int(P[i][s]) == s
-            assert int((D[i] >= 0).sum()) == int(size[lab[s]]), f"mixed graph {gi} lane {i}: reach"
+        idx = [k for k in range(len(gos)) if gos[k] == gi]
+        check_batch_properties(f"mixed graph {gi}", oracle.components(e.n, e.src, e.dst),
+                               [srcs[k] for k in idx], [P[k] for k in idx], [D[k] for k in idx])
+    items = ((As[gi], s, [(f"graph {gi} lane {i}", P[i].cpu().numpy(), D[i].cpu().numpy())])
+             for i, (gi, s) in enumerate(zip(gos, srcs)))
+    assert check_all(items, what="mixed") == len(srcs)
     for g in graphs:
         g.free()
 
 
 @pytest.mark.timeout(900)
 def test_fullsize_rmat22_directed(gpu):
-    """R-MAT scale 22 with the pairs as directed edges: sampled sources in
-    full against the directed oracle, in the configuration the benchmark
-    times, and the forced bottom-up and captured-level schedules."""
+    """R-MAT scale 22 with the pairs as directed edges: all 64 benchmark
+    sources in full against the directed oracle, in the configuration the
+    benchmark times, and the forced bottom-up and captured-level schedules
+    on one of them."""
+    import torch
     from paper_1508_03619_amd import inputs, gapbfs as gb
     name = "rmat22d"
     say(f"{name}: generating")
@@ -205,16 +229,19 @@ def test_fullsize_rmat22_directed(gpu):
     g = gb.build_csr(el.n, el.src, el.dst, directed=True)
     say(f"{name}: oracle adjacency")
     A = oracle.Adjacency(el.n, el.src, el.dst, directed=True)
-    for i in (0, 21, 63):
-        say(f"{name}: search {i} (source {srcs[i]}) vs oracle")
-        ref = A.bfs(srcs[i])[0]
-        p, d = run_single(g, srcs[i])
-        assert_valid(A, srcs[i], p, d, ref, what=name)
-        if i == 0:
-            for sch in (dict(direction=2), dict(mode=2)):
-                say(f"{name}: {sch}")
-                p, d = run_single(g, srcs[i], params=sch)
-                assert_valid(A, srcs[i], p, d, ref, what=f"{name} {sch}")
+    p1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    d1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def items():
+        for i, s in enumerate(srcs):
+            res = [("default", *run_single(g, s, p=p1, d=d1))]
+            if i == 0:
+                for sch in (dict(direction=2), dict(mode=2)):
+                    res.append((str(sch), *run_single(g, s, params=sch, p=p1, d=d1)))
+            yield A, s, res
+
+    say(f"{name}: 64 sources vs the directed oracle")
+    assert check_all(items(), what=name) == 66
     g.free()
 
 
