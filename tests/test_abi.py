@@ -108,3 +108,20 @@ def test_no_device_reports_edevice(lib):
     st = lib.gap_build_csr(3, 2, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                            d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0, None, ctypes.byref(out))
     assert st == gapbfs.GAP_EDEVICE
+
+
+def test_package_reexports_what_the_gpu_tests_call():
+    """The GPU tests call the binding through the package object that the
+    ``gpu`` fixture returns: every public call must be reachable there."""
+    import ast
+    import paper_1508_03619_amd as pkg
+    used = set()
+    for fn in os.listdir(os.path.join(ROOT, "tests")):
+        if fn.endswith(".py"):
+            tree = ast.parse(open(os.path.join(ROOT, "tests", fn)).read())
+            for node in ast.walk(tree):
+                if (isinstance(node, ast.Attribute) and isinstance(node.value, ast.Name)
+                        and node.value.id in ("gpu", "gb") and not node.attr.startswith("_")):
+                    used.add(node.attr)
+    missing = sorted(a for a in used if not hasattr(pkg, a))
+    assert not missing, missing

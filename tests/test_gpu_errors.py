@@ -50,7 +50,10 @@ def test_single_search_timeout_is_sticky(gpu):
     with pytest.raises(gb.GapError) as ei:
         gb.bfs(g, s, p, d, params={"wait_limit_us": 1}, stats=True)
     assert ei.value.status == gb.GAP_ETIMEOUT
-    gb.stream_status()  # the sticky word holds it too; clear it
+    with pytest.raises(gb.GapError) as ei:  # the sticky word holds it too
+        gb.stream_status()
+    assert ei.value.status == gb.GAP_ETIMEOUT
+    gb.stream_status()  # and reading it cleared it
     gb.bfs(g, s, p, d)
     torch.cuda.synchronize()
     gb.stream_status()
