@@ -156,6 +156,39 @@ gap_status gap_graph_export_in(const gap_graph *g, int64_t *row_ptr,
 gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent,
                    int32_t *depth, void *stream);
 
+/* Size in bytes of the per-device scratch array of gap_bfs_noalloc. */
+#define GAP_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/*
+ * gap_bfs_noalloc -- gap_bfs for callers that cannot allocate device
+ * memory: work queued under stream capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, outputs and errors as gap_bfs;
+ * always the persistent schedule (one cooperative launch, after a small
+ * kernel that clears the control block), whatever gap_set_params selected
+ * for mode and grid_split; the other parameters apply.
+ * Scratch: every per-search buffer (queues, bitmaps, control block, the
+ * depth array when depth is NULL) lives in one file-scope device array of
+ * GAP_NOALLOC_SCRATCH_BYTES, of which each GPU that runs the call holds its
+ * own copy until the process ends.  The call allocates no device or pinned
+ * memory and creates no event; its first call on a device records the
+ * array's device address (and clears its status word on `stream`).  A
+ * graph needs about 132 bytes per vertex (136 with a NULL depth) plus 2
+ * bytes per adjacency entry (default hub_degree and chunk_edges), e.g. up
+ * to 2^18 vertices with 2^23 entries; a larger one gets GAP_EINVAL and
+ * nothing is queued.
+ * Every call on a GPU shares that GPU's array, and it keeps the previous
+ * call's contents (the call clears what must start at zero): calls that
+ * overlap on one GPU -- on different streams, or from several host threads
+ * -- race and give undefined results.  Serialise them (one stream, or
+ * events).
+ * A search that fails on the device (GAP_ETIMEOUT: a bounded wait gave up)
+ * leaves its outputs undefined and records the error in a status word of
+ * the array, which gap_stream_status returns (and clears) after waiting
+ * for its stream.
+ */
+gap_status gap_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent,
+                           int32_t *depth, void *stream);
+
 /*
  * gap_bfs_batch -- many searches in one multi-source launch.  Lane i
  * searches graph graphs[graph_of_source[i]] from sources[i]; each lane's

@@ -107,6 +107,29 @@ gap_status coop_begin(int dev, hipStream_t s, int k, CoopOrder *o) {
   return GAP_OK;
 }
 
+void coop_prepare(int dev) { (void)coop_state(dev); }
+
+gap_status coop_begin_existing(int dev, hipStream_t s, CoopOrder *o) {
+  CoopState *cs = coop_state(dev);
+  o->lock = std::unique_lock<std::mutex>(cs->mu);
+  if (cs->k < 1) {
+    o->slot = -1;
+    return GAP_OK;
+  }
+  o->slot = (int)(cs->next % (unsigned long long)cs->k);
+  const size_t i = (size_t)o->slot;
+  if (cs->recorded[i] && cs->on[i] != s) GAP_HIP(hipStreamWaitEvent(s, cs->ev[i], 0));
+  return GAP_OK;
+}
+
+gap_status coop_end_existing(int dev, hipStream_t s, CoopOrder *o) {
+  if (o->slot < 0) {
+    o->lock.unlock();
+    return GAP_OK;
+  }
+  return coop_end(dev, s, o);
+}
+
 gap_status coop_end(int dev, hipStream_t s, CoopOrder *o) {
   CoopState *cs = coop_state(dev);
   hipError_t e = hipEventRecord(cs->ev[(size_t)o->slot], s);
@@ -432,6 +455,8 @@ gap_status stream_status(hipStream_t stream) {
       if (first == GAP_OK) first = code;
     }
   }
+  const gap_status na = noalloc_status(stream);
+  if (first == GAP_OK) first = na;
   if (first != GAP_OK)
     set_error("a search queued on this stream failed on the device (%s); its outputs are undefined",
               first == GAP_ETIMEOUT ? "a bounded wait gave up" : "inconsistent state");
@@ -673,6 +698,20 @@ gap_status gap_bfs_ex(const gap_graph *g, int32_t source, int32_t *parent, int32
 gap_status gap_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
                    void *stream) {
   return gap_bfs_ex(g, source, parent, depth, stream, nullptr, nullptr, 0, nullptr);
+}
+
+gap_status gap_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
+                           void *stream) {
+  clear_error();
+  if (!g || !parent) {
+    set_error("gap_bfs_noalloc: NULL %s", g ? "parent" : "graph");
+    return GAP_EINVAL;
+  }
+  if (source < 0 || (int64_t)source >= g->n) {
+    set_error("gap_bfs_noalloc: source %d outside [0, %lld)", source, (long long)g->n);
+    return GAP_EINVAL;
+  }
+  return run_bfs_noalloc(g, source, parent, depth, (hipStream_t)stream);
 }
 
 gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,

@@ -7,6 +7,7 @@
 //  * graph: the same per-level kernels captured into a hipGraph of K levels
 //    that is replayed until the device reports the search done.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "bfs_kernels.h"
@@ -588,6 +589,160 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
   }
   if (num_levels) *num_levels = levels;
   return GAP_OK;
+}
+
+// ---- a search that allocates nothing ------------------------------------------------
+// For callers that cannot allocate device memory (work queued under stream
+// capture, serving loops, harnesses that forbid allocation): the per-search
+// scratch of the persistent schedule lives in one file-scope device array.
+// Each GPU holds its own copy (zero-initialised data of the code object)
+// until the process ends.  Host code names the array only to look up its
+// device address, once per device; kernels get that address as an argument.
+constexpr size_t kNoAllocBytes = (size_t)GAP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_na_mu;
+static unsigned char *g_na_ptr[kNoAllocMaxDevices];  // device address of `scratch`, per device
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t words, uint32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = v;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Offsets into the array for one search: [0, 256) holds the status word.
+struct NoAllocLayout {
+  size_t ctl, bm0, bm1, vbm, depth, q0, q1, c0, c1, total;
+  int64_t ccap;
+};
+
+static NoAllocLayout noalloc_layout(int64_t n, int64_t nnz, const gap_params &p, bool need_depth) {
+  NoAllocLayout L{};
+  const size_t words = (size_t)((n + kWave - 1) / kWave + 1);
+  L.ccap = nnz / p.chunk_edges + nnz / p.hub_degree + 2;  // as the pooled workspace
+  size_t o = 256;
+  L.ctl = o;
+  o = align256(o + sizeof(Ctl));
+  L.bm0 = o;
+  o = align256(o + sizeof(uint64_t) * words);
+  L.bm1 = o;
+  o = align256(o + sizeof(uint64_t) * words);
+  L.vbm = o;
+  o = align256(o + sizeof(uint64_t) * words);
+  L.depth = o;
+  if (need_depth) o = align256(o + sizeof(int32_t) * (size_t)n);
+  L.q0 = o;
+  o = align256(o + sizeof(int32_t) * (size_t)n * kGroups);
+  L.q1 = o;
+  o = align256(o + sizeof(int32_t) * (size_t)n * kGroups);
+  L.c0 = o;
+  o = align256(o + sizeof(int2) * (size_t)L.ccap * kGroups);
+  L.c1 = o;
+  o = align256(o + sizeof(int2) * (size_t)L.ccap * kGroups);
+  L.total = o;
+  return L;
+}
+
+// Device address of the array on `dev` (current), looked up on the first
+// call for that device; the status word is cleared then, on `stream`.
+static gap_status noalloc_base(int dev, hipStream_t stream, unsigned char **out) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) {
+    set_error("gap_bfs_noalloc: device %d beyond the %d supported", dev, kNoAllocMaxDevices);
+    return GAP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) {
+      set_error("hipGetSymbolAddress(scratch) returned NULL");
+      return GAP_EDEVICE;
+    }
+    k_fill_u32<<<1, 64, 0, stream>>>(reinterpret_cast<uint32_t *>(ptr), 64, 0u);
+    GAP_HIP(hipGetLastError());
+    coop_prepare(dev);  // the launch-order bookkeeping entry of the device
+    g_na_ptr[dev] = reinterpret_cast<unsigned char *>(ptr);
+  }
+  *out = g_na_ptr[dev];
+  return GAP_OK;
+}
+
+gap_status run_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
+                           hipStream_t stream) {
+  const DeviceInfo *di = nullptr;
+  gap_status st = device_info(g->device, &di);
+  if (st != GAP_OK) return st;
+  GAP_HIP(hipSetDevice(g->device));
+  gap_params p = params_current();
+  const NoAllocLayout L = noalloc_layout(g->n, g->nnz, p, depth == nullptr);
+  if (L.total > kNoAllocBytes) {
+    set_error("gap_bfs_noalloc: the graph (n = %lld, %lld entries) needs %zu bytes of scratch; "
+              "the array holds %zu",
+              (long long)g->n, (long long)g->nnz, L.total, kNoAllocBytes);
+    return GAP_EINVAL;
+  }
+  unsigned char *base = nullptr;
+  st = noalloc_base(g->device, stream, &base);
+  if (st != GAP_OK) return st;
+  SearchArgs a{};
+  a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->n, g->nnz, g->directed};
+  a.parent = parent;
+  a.depth = depth ? depth : reinterpret_cast<int32_t *>(base + L.depth);
+  a.source = source;
+  a.Q.q0 = reinterpret_cast<int32_t *>(base + L.q0);
+  a.Q.q1 = reinterpret_cast<int32_t *>(base + L.q1);
+  a.Q.c0 = reinterpret_cast<int2 *>(base + L.c0);
+  a.Q.c1 = reinterpret_cast<int2 *>(base + L.c1);
+  a.Q.n = g->n;
+  a.Q.ccap = L.ccap;
+  a.bm0 = reinterpret_cast<uint64_t *>(base + L.bm0);
+  a.bm1 = reinterpret_cast<uint64_t *>(base + L.bm1);
+  a.vbm = reinterpret_cast<uint64_t *>(base + L.vbm);
+  a.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
+  a.ctl_clear = nullptr;
+  a.sticky = reinterpret_cast<int *>(base);
+  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier, 0, 0};
+  set_wait_limits(a.p, p.wait_limit_us);
+  a.recs = nullptr;
+  a.max_recs = 0;
+  // one cooperative launch (grid_split 1), ordered after the persistent
+  // launches of the device's existing ring; no event is created
+  p.grid_split = 1;
+  CoopOrder order;
+  st = coop_begin_existing(g->device, stream, &order);
+  if (st != GAP_OK) return st;
+  static_assert(sizeof(Ctl) % sizeof(uint32_t) == 0, "Ctl is cleared word by word");
+  k_fill_u32<<<8, 256, 0, stream>>>(reinterpret_cast<uint32_t *>(a.ctl),
+                                    (int64_t)(sizeof(Ctl) / sizeof(uint32_t)), 0u);
+  hipError_t e = hipGetLastError();
+  st = e == hipSuccess ? dispatch_persistent<false>(a, di, p, stream) : hip_fail(e, "k_fill_u32");
+  const gap_status st2 = coop_end_existing(g->device, stream, &order);
+  if (st != GAP_OK) return st;
+  return st2;
+}
+
+// The no-allocation search's status word on every device where it ran,
+// read after waiting for `stream`: the first non-zero one is returned and
+// cleared.
+gap_status noalloc_status(hipStream_t stream) {
+  gap_status first = GAP_OK;
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  for (int dev = 0; dev < kNoAllocMaxDevices; ++dev) {
+    if (!g_na_ptr[dev]) continue;
+    GAP_HIP(hipSetDevice(dev));
+    GAP_HIP(hipStreamSynchronize(stream));
+    int code = 0;
+    GAP_HIP(hipMemcpy(&code, g_na_ptr[dev], sizeof(int), hipMemcpyDeviceToHost));
+    if (code != 0) {
+      const int zero = 0;
+      GAP_HIP(hipMemcpy(g_na_ptr[dev], &zero, sizeof(int), hipMemcpyHostToDevice));
+      if (first == GAP_OK) first = code;
+    }
+  }
+  return first;
 }
 
 }  // namespace gap

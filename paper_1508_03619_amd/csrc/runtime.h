@@ -144,6 +144,12 @@ struct CoopOrder {
 };
 gap_status coop_begin(int dev, hipStream_t s, int k, CoopOrder *o);
 gap_status coop_end(int dev, hipStream_t s, CoopOrder *o);
+// The same ordering for a launch that may not create events: it joins the
+// device's ring as it is (of any size) and orders nothing when no ring
+// exists yet.  coop_prepare creates the device's (empty) entry.
+void coop_prepare(int dev);
+gap_status coop_begin_existing(int dev, hipStream_t s, CoopOrder *o);
+gap_status coop_end_existing(int dev, hipStream_t s, CoopOrder *o);
 
 // Launches a kernel whose workgroups wait on each other (grid barriers).
 // max_grid is the largest grid that is resident at once on the whole
@@ -166,6 +172,13 @@ gap_status params_check(const gap_params &p);
 gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
                    hipStream_t stream, const gap_params &p, gap_level_stat *stats,
                    int32_t max_levels, int32_t *num_levels);
+// The same search (persistent schedule) with every scratch buffer in a
+// file-scope device array of GAP_NOALLOC_SCRATCH_BYTES: no allocation.
+gap_status run_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent, int32_t *depth,
+                           hipStream_t stream);
+// Waits for `stream`, then returns and clears the first failure recorded by
+// no-allocation searches.
+gap_status noalloc_status(hipStream_t stream);
 // Implemented in msbfs.hip
 gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          const int32_t *graph_of_source, const int32_t *sources,

@@ -64,7 +64,7 @@ EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
             "gap_device_query", "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
             "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc", "gap_stream_status",
-            "gap_shutdown"]
+            "gap_shutdown", "gap_bfs_noalloc"]
 
 
 def library_path() -> str:
@@ -94,6 +94,7 @@ def load():
         L.gap_graph_export_in.argtypes = [vp, i64p, i32p]
         L.gap_graph_directed.argtypes = [vp]
         L.gap_bfs.argtypes = [vp, i32, vp, vp, vp]
+        L.gap_bfs_noalloc.argtypes = [vp, i32, vp, vp, vp]
         L.gap_bfs_ex.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(_Params),
                                  ctypes.POINTER(LevelStat), i32, i32p]
         L.gap_bfs_batch.argtypes = [ctypes.POINTER(vp), i32, i32p, i32p, i32,
@@ -117,7 +118,7 @@ def load():
         L.gap_shutdown.argtypes = []
         L.gap_shutdown.restype = None
         for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_graph_export_in",
-                     "gap_graph_directed", "gap_bfs", "gap_bfs_ex",
+                     "gap_graph_directed", "gap_bfs", "gap_bfs_ex", "gap_bfs_noalloc",
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
                      "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
                      "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc",
@@ -347,6 +348,20 @@ def bfs(g: Graph, source: int, parent, depth=None, stream=None, params: Optional
     _check(L.gap_bfs_ex(g.handle, int(source), _ptr(parent), _ptr(depth), _stream_handle(stream),
                         pp, None, 0, None))
     return None
+
+
+def bfs_noalloc(g: Graph, source: int, parent, depth=None, stream=None):
+    """gap_bfs_noalloc: one search (persistent schedule) whose scratch is the
+    library's per-device array; nothing is allocated.  Graphs whose scratch
+    exceeds NOALLOC_SCRATCH_BYTES raise GapError (GAP_EINVAL)."""
+    L = load()
+    if parent.numel() < g.n or (depth is not None and depth.numel() < g.n):
+        raise ValueError("output buffers shorter than n")
+    _check(L.gap_bfs_noalloc(g.handle, int(source), _ptr(parent), _ptr(depth),
+                             _stream_handle(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # GAP_NOALLOC_SCRATCH_BYTES
 
 
 def bfs_batch(graphs: Sequence[Graph], graph_of_source: Sequence[int], sources: Sequence[int],
