@@ -368,6 +368,13 @@ typedef struct gap_params {
                             without a finished small level).  A wait that
                             gives up ends the search with GAP_ETIMEOUT; every
                             kernel still exits. */
+  int32_t bu_mapping;    /* persistent single-source schedule, bottom-up
+                            steps: 0 = each workgroup owns a contiguous range
+                            of vertices and its lanes are refilled with new
+                            vertices as held ones finish (when the range fits
+                            the workgroup's LDS bitmap: up to 4096 64-vertex
+                            words per workgroup), 1 = each wave keeps a fixed
+                            set of 4 words until all their vertices finish */
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

@@ -197,6 +197,7 @@ static gap_params default_params() {
   p.grid_split = 1;
   p.small_frontier = 32768;
   p.lds_bitmap = 1;
+  p.bu_mapping = 0;
   return p;
 }
 
@@ -250,6 +251,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.lds_bitmap != 0 && p.lds_bitmap != 1) {
     set_error("params: lds_bitmap must be 0 or 1");
+    return GAP_EINVAL;
+  }
+  if (p.bu_mapping != 0 && p.bu_mapping != 1) {
+    set_error("params: bu_mapping must be 0 or 1");
     return GAP_EINVAL;
   }
   if (p.small_frontier < 0) {

@@ -89,6 +89,7 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
   const unsigned int nblocks = gridDim.x;
   const unsigned int nsmall = nblocks < (unsigned)GAP_SMALL_GROUP ? nblocks : (unsigned)GAP_SMALL_GROUP;
   const bool small_enabled = a.p.small > 0 && nblocks > nsmall;
+  const int64_t nwords_all = (a.g.n + kWave - 1) / kWave;
 
   init_vertices(a.g, a.parent, a.depth, a.source, tid, nthreads);
   if (a.ctl_clear) {  // no search uses it now: the one before this has finished with it
@@ -156,7 +157,13 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
     LaneAcc acc;
     if (dir == kTopDown)
       td_step<BLOCK, STATS, true>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
-    else
+    else if (a.p.bu_mapping == 0 && (nwords_all + nblocks - 1) / nblocks <= bu_refill_words<BLOCK>()) {
+      // never on the small group: every workgroup takes its share of the words
+      const int64_t per = (nwords_all + nblocks - 1) / nblocks;
+      const int64_t wlo = (int64_t)blockIdx.x * per < nwords_all ? (int64_t)blockIdx.x * per : nwords_all;
+      const int64_t whi = wlo + per < nwords_all ? wlo + per : nwords_all;
+      bu_step_refill<BLOCK, STATS, GAP_BU_SLOTS>(s, st, acc, wlo, whi, a.lds_bm ? lds_fbm : nullptr);
+    } else
       bu_step<BLOCK, STATS, GAP_BU_WORDS, GAP_BU_ROUND2, false>(s, st, acc, gwave,
                                                                 nwaves,  // never on the small group
                                                                 a.lds_bm ? lds_fbm : nullptr);
@@ -525,7 +532,8 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
   a.bm1 = ws->bm[1];
   a.vbm = ws->bm[2];
   a.ctl = ws->ctl;
-  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier, 0, 0};
+  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier,
+               p.bu_mapping, 0, 0};
   set_wait_limits(a.p, p.wait_limit_us);
   a.sticky = ws->sticky;
   a.recs = want_stats ? ws->recs : nullptr;
@@ -704,7 +712,8 @@ gap_status run_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent, 
   a.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
   a.ctl_clear = nullptr;
   a.sticky = reinterpret_cast<int *>(base);
-  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier, 0, 0};
+  a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier,
+               p.bu_mapping, 0, 0};
   set_wait_limits(a.p, p.wait_limit_us);
   a.recs = nullptr;
   a.max_recs = 0;

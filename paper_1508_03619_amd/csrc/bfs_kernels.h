@@ -583,6 +583,188 @@ __device__ inline int nth_set_bit(uint64_t x, uint32_t k) {
   return pos;
 }
 
+// Bottom-up step with refilled lanes (persistent schedule, no queue).
+// Workgroup b owns the contiguous words [wlo, whi) of the vertex range and
+// hands them to its waves kBuChunk words at a time (an LDS cursor).  A lane
+// holds J vertices at once; every round reads four list entries of each held
+// vertex (one 16-byte load) and probes the frontier bitmap for them; a vertex
+// that found its parent (its first frontier neighbour in list order) or ran
+// out of entries frees its slot, and the wave refills free slots from its
+// chunk before the next round.  So lanes do not idle while a wave's slowest
+// vertices finish, as they would if a wave kept a fixed set of vertices until
+// all of them were done.  Found vertices are collected in an LDS bitmap of the
+// workgroup's words (it reuses the vertex staging, which a step without a
+// queue leaves empty); after the last round the workgroup writes each of its
+// words of the next frontier and of the visited bitmap once.
+// Requires whi - wlo <= bu_refill_words<BLOCK>().
+constexpr int kBuChunk = 16;
+// Vertices a lane holds at once (four keep the kernel within 128 VGPRs only
+// with spills).
+#ifndef GAP_BU_SLOTS
+#define GAP_BU_SLOTS 3
+#endif
+
+template <int BLOCK>
+__host__ __device__ constexpr int64_t bu_refill_words() {
+  return (int64_t)(Stage<BLOCK>::QCAP * sizeof(int32_t) / sizeof(uint64_t));
+}
+
+template <int BLOCK, bool STATS, int J>
+__device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t wlo,
+                               int64_t whi, uint64_t *lfbm) {
+  uint64_t *found = reinterpret_cast<uint64_t *>(st.q);
+  unsigned int *cursor = &st.hbase;
+  const int lane = lane_id();
+  const int64_t nw = whi > wlo ? whi - wlo : 0;
+  if (lfbm) {
+    const int64_t nwords = (a.g.n + kWave - 1) / kWave;
+    for (int64_t i = threadIdx.x; i < nwords; i += BLOCK) lfbm[i] = a.fbm[i];
+  }
+  for (int64_t i = threadIdx.x; i < nw; i += BLOCK) found[i] = 0ull;
+  if (threadIdx.x == 0) *cursor = 0u;
+  __syncthreads();
+  const uint64_t *fb = lfbm ? lfbm : a.fbm;
+  const int32_t *__restrict__ col = a.g.col_in;
+  const int64_t *__restrict__ rp = a.g.row_ptr_in;
+
+  int32_t v[J];    // held vertex, -1 = free slot
+  int64_t e[J];    // next list entry
+  int32_t rem[J];  // entries left
+  int32_t deg[J];  // list length (the frontier-edge count of an undirected find)
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    v[j] = -1;
+    e[j] = 0;
+    rem[j] = 0;
+    deg[j] = 0;
+  }
+  uint64_t win = 0ull;  // this lane's word of the chunk: unvisited bits not yet handed out
+  int64_t wbase = 0;    // first word of the chunk (wave-uniform)
+  uint32_t wleft = 0;   // vertices of the chunk not yet handed out (wave-uniform)
+  bool more = nw > 0;   // chunks left in the range (wave-uniform)
+  for (;;) {
+    // ---- refill the free slots, row by row, in vertex order ----
+    for (;;) {
+      uint64_t fm[J];
+      uint32_t nfree = 0;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        fm[j] = __ballot(v[j] < 0);
+        nfree += (uint32_t)__popcll(fm[j]);
+      }
+      if (nfree == 0u) break;
+      if (wleft == 0u) {
+        if (!more) break;
+        unsigned int c0 = 0;
+        if (lane == 0) c0 = atomicAdd(cursor, (unsigned int)kBuChunk);
+        c0 = uni((uint32_t)__shfl((int)c0, 0, kWave));
+        if ((int64_t)c0 >= nw) {
+          more = false;
+          break;
+        }
+        wbase = wlo + (int64_t)c0;
+        win = (lane < kBuChunk && (int64_t)c0 + lane < nw) ? ~a.vbm[wbase + lane] : 0ull;
+        wleft = uni((uint32_t)wave_sum_u64((unsigned long long)__popcll(win)));
+        continue;
+      }
+      const uint32_t cnt = (uint32_t)__popcll(win);
+      uint32_t tot;
+      const uint32_t off = wave_excl_scan_u32(cnt, tot);
+      if (tot == 0u) {  // the chunk is used up: take the next one
+        wleft = 0u;
+        continue;
+      }
+      const uint32_t take = nfree < tot ? nfree : tot;
+      uint32_t base = 0;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const bool isfree = (fm[j] >> lane) & 1ull;
+        uint32_t r = base + lane_rank(fm[j]);
+        base += (uint32_t)__popcll(fm[j]);
+        const bool gets = isfree && r < take;
+        if (!gets) r = 0;
+        int jw = 0;  // the chunk word holding handed-out position r: largest jw with off <= r
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const uint32_t oc = (uint32_t)__shfl((int)off, jw + step, kWave);
+          if (oc <= r && jw + step < kBuChunk) jw += step;
+        }
+        const uint64_t bw = (uint64_t)__shfl((long long)win, jw, kWave);
+        const uint32_t ow = (uint32_t)__shfl((int)off, jw, kWave);
+        if (gets) {
+          const int64_t vv = (wbase + jw) * kWave + nth_set_bit(bw, r - ow);
+          v[j] = (int32_t)vv;
+          e[j] = rp[vv];
+          rem[j] = (int32_t)(rp[vv + 1] - e[j]);
+          deg[j] = rem[j];
+          if (STATS) acc.unvisited += 1;
+        }
+      }
+      // each chunk word drops the bits it handed out (the lowest ones)
+      const int t = (int)take - (int)off;
+      if (t > 0) win = t >= (int)cnt ? 0ull : (win & ~((2ull << nth_set_bit(win, (uint32_t)t - 1u)) - 1ull));
+      wleft = tot - take;
+    }
+    bool held = false;
+#pragma unroll
+    for (int j = 0; j < J; ++j) held |= v[j] >= 0;
+    if (__ballot(held) == 0ull) break;
+    // ---- one round: four entries of every held vertex ----
+    int32_t u[J][4];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      i32x4_a4 w = {-1, -1, -1, -1};
+      if (v[j] >= 0) w = *reinterpret_cast<const i32x4_a4 *>(col + e[j]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[j][k] = (v[j] >= 0 && k < rem[j]) ? w[k] : -1;
+    }
+    bool hit[J][4];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        hit[j][k] = u[j][k] >= 0 && ((fb[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (v[j] < 0) continue;
+      int32_t pu = -1;
+#pragma unroll
+      for (int k = 3; k >= 0; --k)
+        if (hit[j][k]) pu = u[j][k];
+      if (STATS) {
+        int used = 0;
+        for (int k = 0; k < 4 && k < rem[j]; ++k) {
+          ++used;
+          if (hit[j][k]) break;
+        }
+        acc.scanned += used;
+      }
+      if (pu >= 0) {
+        const int32_t vv = v[j];
+        a.parent[vv] = pu;
+        a.depth[vv] = a.d + 1;
+        atomicOr((unsigned long long *)&found[(vv >> 6) - wlo], 1ull << (vv & 63));
+        // the next frontier's edges are out-edges: on a directed graph the
+        // in-degree held here is not the count the top-down side needs
+        const int64_t dv = a.g.directed ? a.g.row_ptr[vv + 1] - a.g.row_ptr[vv] : (int64_t)deg[j];
+        acc.mf += (unsigned long long)dv;
+        acc.nv += 1;
+        v[j] = -1;
+      } else {
+        e[j] += 4;
+        rem[j] -= 4;
+        if (rem[j] <= 0) v[j] = -1;
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < nw; i += BLOCK) {
+    const uint64_t b = found[i];
+    a.nbm[wlo + i] = b;
+    if (b) a.vbm[wlo + i] |= b;
+  }
+}
+
 // Bottom-up -> top-down: F_d, held as a bitmap by the bottom-up steps
 // (which do not build queues), becomes the vertex queue and hub chunk
 // items of buffer set bs_out, as a top-down step would have appended them.

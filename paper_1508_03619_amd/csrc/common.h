@@ -102,6 +102,7 @@ struct Ctl {
 struct Params {
   int32_t alpha, beta, direction, hub, chunk;
   int32_t small;  // top-down levels with |F| and m_f at most this run on the small group
+  int32_t bu_mapping;  // persistent bottom-up steps: 0 refilled lanes, 1 fixed words per wave
   uint64_t wait;       // bound of one barrier wait (real-time ticks)
   uint64_t wait_park;  // bound of a parked workgroup's wait without progress
 };

@@ -39,7 +39,8 @@ class _Params(ctypes.Structure):
                 ("graph_chunk", ctypes.c_int32), ("batch_mode", ctypes.c_int32),
                 ("batch_alpha", ctypes.c_int32), ("batch_beta", ctypes.c_int32),
                 ("grid_split", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
-                ("lds_bitmap", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32)]
+                ("lds_bitmap", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32),
+                ("bu_mapping", ctypes.c_int32)]
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_]
@@ -362,7 +363,6 @@ def bfs_noalloc(g: Graph, source: int, parent, depth=None, stream=None):
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # GAP_NOALLOC_SCRATCH_BYTES
-
 
 def bfs_batch(graphs: Sequence[Graph], graph_of_source: Sequence[int], sources: Sequence[int],
               parents: Sequence, depths: Optional[Sequence] = None, stream=None):

@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 SCHEDULES = [dict(mode=m, direction=d) for m in (0, 1, 2) for d in (0, 1, 2)] + \
     [dict(mode=0, direction=d, small_frontier=sf) for d in (0, 1) for sf in (0, 1 << 30)] + \
-    [dict(mode=0, direction=d, lds_bitmap=0) for d in (0, 2)]
+    [dict(mode=0, direction=d, lds_bitmap=0) for d in (0, 2)] + \
+    [dict(mode=0, direction=d, bu_mapping=1) for d in (0, 2)]
 
 
 def small_cases():
@@ -243,7 +244,10 @@ def test_small_group_levels(gpu, block):
 
 def test_lds_frontier_bitmap(gpu):
     """Bottom-up steps with the frontier bitmap in LDS (graphs small enough)
-    and in L2 (a graph too large for LDS, or the option off)."""
+    and in L2 (a graph too large for LDS, or the option off), with refilled
+    lanes over per-workgroup ranges (ranges of 4, 128 and 61 words: shorter
+    than a chunk, several chunks, a ragged last chunk) and with fixed words
+    per wave."""
     from paper_1508_03619_amd import inputs
     for el, what in [(inputs.rmat(16, 16, seed=55), "rmat16"), (inputs.grid(1000, 1000, seed=56), "grid1000"),
                      (inputs.urand(1 << 21, 1 << 24, seed=57), "urand2M")]:
@@ -252,10 +256,12 @@ def test_lds_frontier_bitmap(gpu):
             ref = A.bfs(int(src))[0]
             for lds in (0, 1):
                 for direction in (0, 2):
-                    say(f"lds bitmap {what} lds={lds} dir={direction}")
-                    parent, depth = device_bfs(gpu, g, int(src), params=dict(
-                        lds_bitmap=lds, direction=direction))
-                    assert_valid(A, int(src), parent, depth, ref, what=f"{what} lds={lds}")
+                    for bu in (0, 1):
+                        say(f"lds bitmap {what} lds={lds} dir={direction} bu_mapping={bu}")
+                        parent, depth = device_bfs(gpu, g, int(src), params=dict(
+                            lds_bitmap=lds, direction=direction, bu_mapping=bu))
+                        assert_valid(A, int(src), parent, depth, ref,
+                                     what=f"{what} lds={lds} bu_mapping={bu}")
         g.free()
 
 
