@@ -50,6 +50,8 @@ typedef int32_t gap_status;
 #define GAP_EINVAL (-1)    /* bad argument (NULL pointer, ID out of range) */
 #define GAP_ENOMEM (-2)    /* device or host allocation failed */
 #define GAP_EDEVICE (-3)   /* no HIP device, or a HIP runtime error */
+#define GAP_EBUSY (-4)     /* the call cannot proceed now (a full request ring,
+                              a server holding requests on another graph) */
 #define GAP_EINTERNAL (-5) /* the device reported an inconsistent state */
 #define GAP_ETIMEOUT (-6)  /* a bounded device-side wait gave up */
 
@@ -219,6 +221,61 @@ gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          int32_t *const *parents, int32_t *const *depths,
                          void *stream);
 
+/* ---- continuous batching (serving) -----------------------------------------
+ * A server keeps one multi-source search running on the device for the
+ * single-source queries of one graph at a time (Section 2.1 output per
+ * query): up to 64 queries are the bits of a per-vertex 64-bit word; a query
+ * submitted while the search runs joins it at the next level boundary
+ * (its depths counted from that level) in a free lane, and a query whose
+ * frontier is empty completes on its own, freeing its lane.  Every query's
+ * result is exactly what gap_bfs returns for its (graph, source): the same
+ * depths, valid parents.
+ * Threading: one host thread at a time per server.  The server's launches
+ * are queued on its stream, which they keep busy while they run; read a
+ * completed query's outputs on another stream.
+ */
+typedef struct gap_server gap_server;
+
+/*
+ * gap_serve_open -- a server for graphs of at most max_vertices vertices
+ * and max_entries adjacency entries, launching on `stream` (of the current
+ * device).  Allocates its device state (about 152 bytes per vertex plus
+ * 2 bytes per entry at the default hub_degree/chunk_edges) and a pinned
+ * request/completion ring shared with the device.
+ * Errors: GAP_EINVAL (NULL out, sizes out of range), GAP_ENOMEM,
+ * GAP_EDEVICE.
+ */
+gap_status gap_serve_open(int64_t max_vertices, int64_t max_entries,
+                          void *stream, gap_server **out);
+
+/*
+ * gap_serve_submit -- queues one query: BFS of g (undirected, built on the
+ * server's device, within the server's sizes) from `source`, writing
+ * int32[n] parent and (when not NULL) depth on the device, as gap_bfs does.
+ * The outputs are final once gap_serve_poll returns `qid`.  The query joins
+ * a running launch at its next level boundary, or the call launches one.
+ * Errors: GAP_EINVAL (NULL server, graph or parent, source out of range, a
+ * directed or too large graph), GAP_EBUSY (256 queries in flight: poll
+ * first; or the server still holds queries on another graph),
+ * GAP_ENOMEM, GAP_EDEVICE.
+ */
+gap_status gap_serve_submit(gap_server *s, const gap_graph *g, int64_t qid,
+                            int32_t source, int32_t *parent, int32_t *depth);
+
+/*
+ * gap_serve_poll -- stores the ids of up to `max` completed queries (in
+ * completion order) at qids and their number at *count; does not wait.
+ * Returns GAP_ETIMEOUT or GAP_EINTERNAL once if a launch failed on the
+ * device (the queries it held are lost).  Launches again when requests are
+ * waiting and no launch is left to take them.
+ */
+gap_status gap_serve_poll(gap_server *s, int64_t *qids, int32_t max,
+                          int32_t *count);
+
+/* Waits for the server's launches (queries in flight finish) and releases
+ * it (NULL-safe). */
+gap_status gap_serve_close(gap_server *s);
+
 /* gap_bc flag: return the raw sums (no division by the largest score). */
 #define GAP_BC_RAW 1u
 
@@ -375,6 +432,11 @@ typedef struct gap_params {
                             the workgroup's LDS bitmap: up to 4096 64-vertex
                             words per workgroup), 1 = each wave keeps a fixed
                             set of 4 words until all their vertices finish */
+  int32_t serve_window_us; /* gap_serve_*: a serving launch takes new
+                            requests into free lanes at level boundaries for
+                            this long after it starts, then finishes the
+                            searches it holds and exits (0 = it takes
+                            requests at its first boundary only) */
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

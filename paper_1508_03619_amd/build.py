@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgapbfs.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "bfs.hip", "msbfs.hip", "build_csr.hip", "bc.hip", "sssp.hip", "cc.hip"]
+SOURCES = ["api.hip", "bfs.hip", "msbfs.hip", "build_csr.hip", "bc.hip", "sssp.hip", "cc.hip",
+           "serve.hip"]
 ARCH = os.environ.get("GAP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -198,6 +198,7 @@ static gap_params default_params() {
   p.small_frontier = 32768;
   p.lds_bitmap = 1;
   p.bu_mapping = 0;
+  p.serve_window_us = 5000;
   return p;
 }
 
@@ -251,6 +252,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.lds_bitmap != 0 && p.lds_bitmap != 1) {
     set_error("params: lds_bitmap must be 0 or 1");
+    return GAP_EINVAL;
+  }
+  if (p.serve_window_us < 0) {
+    set_error("params: serve_window_us must be >= 0");
     return GAP_EINVAL;
   }
   if (p.bu_mapping != 0 && p.bu_mapping != 1) {

@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "libgapbfs.so")
 _lib = None
 _lock = threading.Lock()
 
-GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_EDEVICE, GAP_EINTERNAL, GAP_ETIMEOUT = 0, -1, -2, -3, -5, -6
+GAP_OK, GAP_EINVAL, GAP_ENOMEM, GAP_EDEVICE, GAP_EBUSY, GAP_EINTERNAL, GAP_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 MODE_PERSISTENT, MODE_LEVELS, MODE_GRAPH = 0, 1, 2
 DIR_AUTO, DIR_TOPDOWN, DIR_BOTTOMUP = 0, 1, 2
 
@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
                 ("batch_alpha", ctypes.c_int32), ("batch_beta", ctypes.c_int32),
                 ("grid_split", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
                 ("lds_bitmap", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32),
-                ("bu_mapping", ctypes.c_int32)]
+                ("bu_mapping", ctypes.c_int32), ("serve_window_us", ctypes.c_int32)]
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_]
@@ -65,7 +65,8 @@ EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
             "gap_device_query", "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
             "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc", "gap_stream_status",
-            "gap_shutdown", "gap_bfs_noalloc"]
+            "gap_shutdown", "gap_bfs_noalloc", "gap_serve_open", "gap_serve_submit",
+            "gap_serve_poll", "gap_serve_close"]
 
 
 def library_path() -> str:
@@ -96,6 +97,10 @@ def load():
         L.gap_graph_directed.argtypes = [vp]
         L.gap_bfs.argtypes = [vp, i32, vp, vp, vp]
         L.gap_bfs_noalloc.argtypes = [vp, i32, vp, vp, vp]
+        L.gap_serve_open.argtypes = [i64, i64, vp, ctypes.POINTER(vp)]
+        L.gap_serve_submit.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.gap_serve_poll.argtypes = [vp, i64p, i32, i32p]
+        L.gap_serve_close.argtypes = [vp]
         L.gap_bfs_ex.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(_Params),
                                  ctypes.POINTER(LevelStat), i32, i32p]
         L.gap_bfs_batch.argtypes = [ctypes.POINTER(vp), i32, i32p, i32p, i32,
@@ -123,7 +128,8 @@ def load():
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
                      "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
                      "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc",
-                     "gap_stream_status"):
+                     "gap_stream_status", "gap_serve_open", "gap_serve_submit", "gap_serve_poll",
+                     "gap_serve_close"):
             getattr(L, name).restype = ctypes.c_int32
         _lib = L
         # release the library's scratch, events and captured graphs before
@@ -363,6 +369,52 @@ def bfs_noalloc(g: Graph, source: int, parent, depth=None, stream=None):
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # GAP_NOALLOC_SCRATCH_BYTES
+
+SERVE_RING = 256  # queries a server holds in flight at most
+
+
+class Server:
+    """gap_serve_*: continuous batching of single-source queries on one graph
+    at a time.  ``submit`` returns False when the server cannot take the
+    query now (GAP_EBUSY: its ring is full, or it still holds queries on
+    another graph); ``poll`` returns the ids of completed queries, whose
+    outputs are then final (read them on a stream other than the server's)."""
+
+    def __init__(self, max_vertices: int, max_entries: int, stream=None):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.gap_serve_open(int(max_vertices), int(max_entries), _stream_handle(stream),
+                                ctypes.byref(h)))
+        self.handle = h
+        self.max_vertices, self.max_entries = int(max_vertices), int(max_entries)
+        self._buf = (ctypes.c_int64 * SERVE_RING)()
+
+    def submit(self, g: Graph, qid: int, source: int, parent, depth=None) -> bool:
+        if parent.numel() < g.n or (depth is not None and depth.numel() < g.n):
+            raise ValueError("output buffers shorter than n")
+        st = load().gap_serve_submit(self.handle, g.handle, int(qid), int(source), _ptr(parent),
+                                     _ptr(depth))
+        if st == GAP_EBUSY:
+            return False
+        _check(st)
+        return True
+
+    def poll(self) -> list:
+        n = ctypes.c_int32(0)
+        _check(load().gap_serve_poll(self.handle, self._buf, SERVE_RING, ctypes.byref(n)))
+        return [int(self._buf[i]) for i in range(n.value)]
+
+    def close(self):
+        if self.handle:
+            load().gap_serve_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 def bfs_batch(graphs: Sequence[Graph], graph_of_source: Sequence[int], sources: Sequence[int],
               parents: Sequence, depths: Optional[Sequence] = None, stream=None):
