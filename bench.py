@@ -75,6 +75,29 @@ def algorithmic_bytes(recs, n, directed=False) -> int:
     return int(total)
 
 
+def batch_algorithmic_bytes(recs, n, lanes) -> int:
+    """Bytes one multi-source launch must move, from its per-level records
+    (W = ceil(lanes / 64) 64-bit words per vertex for each bitset, S = lanes):
+    init 24 W n (visited and frontier cleared, next cleared by the first
+    advance); outputs 8 S n, written once; every level's dense advance
+    24 W n (visited |= frontier, frontier read, next cleared);
+    top-down level, A frontier vertices with N_A edges:
+        8 W |A| (their frontier words) + 16 |A| (row offsets)
+        + N_A (4 + 8 W) (column entry and the neighbour's visited word);
+    bottom-up level, U searched vertices, S_U scanned entries:
+        16 |U| (row offsets) + 16 W |U| (visited and next words)
+        + S_U (4 + 8 W) (column entry and the neighbour's frontier word)."""
+    W = max(1, -(-int(lanes) // 64))
+    total = 24 * W * n + 8 * int(lanes) * n
+    for r in recs:
+        total += 24 * W * n
+        if r["direction"] == 1:
+            total += 8 * W * r["frontier"] + 16 * r["frontier"] + r["frontier_edges"] * (4 + 8 * W)
+        else:
+            total += 16 * r["unvisited"] + 16 * W * r["unvisited"] + r["scanned"] * (4 + 8 * W)
+    return int(total)
+
+
 class GraphCase:
     def __init__(self, name, el, gb, torch, nsrc, src_seed):
         from paper_1508_03619_amd import inputs
@@ -450,10 +473,14 @@ def leg_mixed(gb, torch, inputs, stream):
 
 
 def leg_serving(gb, torch, nq):
-    """Serving pool of 32 resident graphs: saturation throughput R_sat from a
-    closed loop (16 clients per launch slot, each sending its next query when
-    the previous completes), then Poisson arrivals at 0.25, 0.6 and 0.9 of
-    R_sat."""
+    """Serving pool of 32 resident graphs, two loops over the same arrivals:
+    launch-granular batching (a launch takes the queries waiting when it
+    starts) and continuous batching (queries join running searches of their
+    graph at level boundaries, gap_serve_*).  For each: saturation throughput
+    R_sat from a closed loop (16 clients per slot), then Poisson arrivals at
+    0.25, 0.6 and 0.9 of R_sat.  Admission: the outputs of queries in flight
+    must fit a budget of 512 MiB (the working sets of the launches are
+    resident beside it and reported)."""
     from paper_1508_03619_amd import serving as sv
     t0 = time.time()
     spec = sv.pool_spec()
@@ -461,45 +488,61 @@ def leg_serving(gb, torch, nq):
     ces = [component_edges(g, el) for g, el in zip(pool.graphs, pool.edges)]
     pool.edges = [None] * len(pool.edges)
     slots, lanes = 8, 64
-    budget = 8 << 30
-    ex = sv.GpuExecutor(pool.graphs, slots=slots, sources=pool.sources)
+    budget = 512 << 20
     out = {"graphs": len(pool.graphs), "sum_n": int(sum(pool.sizes)), "slots": slots,
            "max_lanes": lanes, "budget_bytes": budget,
-           "workspace_bound_bytes": pool.workspace_bytes(slots, lanes),
            "build_s": round(time.time() - t0, 1)}
 
-    def run(rate, n, seed, clients=0):
+    def run(ex, continuous, rate, n, seed, clients=0):
         qs = sv.poisson_queries(rate, n, pool.sources, seed)
         src = sv.ClosedArrivals(clients, n, lambda k: qs[k]) if clients else qs
         sched = sv.Scheduler(pool.sizes, budget_bytes=budget, max_lanes=lanes)
         t = time.perf_counter()
-        done = sv.serve(ex, sched, src)
+        done = (sv.serve_continuous if continuous else sv.serve)(ex, sched, src)
         wall = time.perf_counter() - t
         summ = sv.latency_summary(done, skip=n // 10)
         kept = sorted(done, key=lambda q: (q.arrival, q.qid))[n // 10:]
         span = max(q.done for q in kept) - min(q.arrival for q in kept)
         summ["gteps"] = sum(int(ces[q.graph][q.source]) for q in kept) / span / 1e9
         summ["peak_admitted_bytes"] = sched.peak_used
+        summ["admission_waits"] = sched.admission_waits
         summ["launches"] = dict(ex.launch_kinds)
         ex.launch_kinds.clear()
         return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}, wall
 
-    clients = 16 * slots
-    try:
-        run(0.0, 300, 1, clients)  # warm-up: workspaces, code objects
-        s, wall = run(0.0, nq, 776, clients)
+    def rates(ex, continuous, tag):
+        res = {}
+        clients = 16 * slots
+        run(ex, continuous, 0.0, 300, 1, clients)  # warm-up: workspaces, code objects
+        s, wall = run(ex, continuous, 0.0, nq, 776, clients)
         rsat = s["throughput_qps"]
-        out["r_sat_qps"] = round(rsat, 1)
-        out["closed_loop_clients"] = clients
-        out["closed"] = s
-        log(f"serving closed loop ({clients} clients): R_sat={rsat:.1f} q/s {s}")
+        res["r_sat_qps"] = round(rsat, 1)
+        res["closed_loop_clients"] = clients
+        res["closed"] = s
+        log(f"serving {tag} closed loop ({clients} clients): R_sat={rsat:.1f} q/s {s}")
         for k, f in enumerate((0.25, 0.6, 0.9)):
-            s, wall = run(f * rsat, nq, 777 + k)
+            s, wall = run(ex, continuous, f * rsat, nq, 777 + k)
             s["offered_qps"] = round(f * rsat, 1)
-            out[f"rate_{f}"] = s
-            log(f"serving at {f} R_sat: {s}")
+            res[f"rate_{f}"] = s
+            log(f"serving {tag} at {f} R_sat: {s}")
+        return res
+
+    try:
+        ex = sv.GpuExecutor(pool.graphs, slots=slots, sources=pool.sources)
+        try:
+            out["launch_granular"] = rates(ex, False, "launch-granular")
+        finally:
+            ex.close()
+        torch.cuda.synchronize()
+        ex = sv.ContinuousExecutor(pool.graphs, slots=slots, lanes=lanes, sources=pool.sources)
+        try:
+            out["continuous_workspace_bytes"] = int(
+                slots * (152 * max(pool.sizes) + 2 * max(g.nnz for g in pool.graphs)))
+            out["continuous_single_search_graphs"] = sorted(int(x) for x in ex.single_graphs)
+            out["continuous"] = rates(ex, True, "continuous")
+        finally:
+            ex.close()
     finally:
-        ex.close()
         pool.free()
     return out
 
@@ -798,6 +841,11 @@ def main():
             ns = len(c.sources)
             parents = [torch.empty(c.g.n, dtype=torch.int32, device="cuda") for _ in range(ns)]
             depths = [torch.empty(c.g.n, dtype=torch.int32, device="cuda") for _ in range(ns)]
+            brecs = gb.bfs_batch([c.g], [0] * ns, [int(s) for s in c.sources], parents, depths,
+                                 stats=True)
+            gb.stream_status()
+            detail[c.name]["batch64_alg_bytes"] = batch_algorithmic_bytes(brecs, c.g.n, ns)
+            detail[c.name]["batch64_levels"] = len(brecs)
             gb.bfs_batch([c.g], [0] * ns, [int(s) for s in c.sources], parents, depths)
             torch.cuda.synchronize()
             e0.record(stream)
@@ -817,9 +865,13 @@ def main():
         # the same two 64-lane batches) against the measured batch times
         bt_mean = float(np.mean([detail[c.name]["batch64_ms"] for c in cases]))
         btraffic = committed_traffic("k_msbfs")
+        balg = float(np.mean([detail[c.name]["batch64_alg_bytes"] for c in cases]))
+        ach = balg / (bt_mean * 1e-3) / 1e9
         detail["batch_roofline"] = {
             "kernel": "k_msbfs", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-            "avg_launch_ms": round(bt_mean, 3), "traffic": btraffic,
+            "avg_launch_ms": round(bt_mean, 3), "alg_bytes_per_launch": int(balg),
+            "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "single_frac": roofline["frac"], "traffic": btraffic,
             "achieved_counted": (round(btraffic / (bt_mean * 1e-3) / 1e9, 1) if btraffic else None),
             "frac_counted": (round(btraffic / (bt_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                              if btraffic else None)}

@@ -432,6 +432,10 @@ typedef struct gap_params {
                             the workgroup's LDS bitmap: up to 4096 64-vertex
                             words per workgroup), 1 = each wave keeps a fixed
                             set of 4 words until all their vertices finish */
+  int32_t batch_words;   /* multi-source tile shape: 64-bit words per vertex
+                            of one graph segment (1, 2 or 4); a graph with
+                            more lanes than 64 * batch_words gets several
+                            segments, each a pass of its own over the graph */
   int32_t serve_window_us; /* gap_serve_*: a serving launch takes new
                             requests into free lanes at level boundaries for
                             this long after it starts, then finishes the
@@ -466,6 +470,23 @@ gap_status gap_bfs_ex(const gap_graph *g, int32_t source, int32_t *parent,
                       int32_t *depth, void *stream, const gap_params *params,
                       gap_level_stat *stats, int32_t max_levels,
                       int32_t *num_levels);
+
+/* gap_bfs_batch with per-level records when `stats` is not NULL (waits for
+ * the batch; copies at most max_levels records and writes the level count
+ * to *num_levels).  A record aggregates the lanes of every graph: frontier =
+ * vertices with some lane's frontier bit, frontier_edges = their degrees,
+ * claimed = the next level's frontier, direction = that of the first
+ * graph's lanes; a bottom-up level counts in `unvisited` the vertices some
+ * lane still needed and in `scanned` the adjacency entries read (a top-down
+ * level reads frontier_edges entries).  At most 128 levels are recorded.
+ * Counting adds device atomics; timed runs pass NULL.  Errors as
+ * gap_bfs_batch, plus GAP_ETIMEOUT / GAP_EINTERNAL from the device. */
+gap_status gap_bfs_batch_ex(const gap_graph *const *graphs, int32_t num_graphs,
+                            const int32_t *graph_of_source,
+                            const int32_t *sources, int32_t num_sources,
+                            int32_t *const *parents, int32_t *const *depths,
+                            void *stream, gap_level_stat *stats,
+                            int32_t max_levels, int32_t *num_levels);
 
 /* Device facts used by the tuner and the benchmark. */
 typedef struct gap_device_info {

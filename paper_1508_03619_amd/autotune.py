@@ -2,8 +2,9 @@
 
 Section 2.3 allows one implementation and one set of tuning parameters for
 all input graphs.  This tuner therefore searches only hardware-facing
-parameters (direction-switch thresholds, workgroup size, hub splitting, the
-level schedule, the batched thresholds) on a fixed tuning set of graphs of
+parameters (direction-switch thresholds, workgroup size and persistent
+workgroups per CU, hub splitting, the bottom-up mapping, the level schedule,
+the batched thresholds and tile shape) on a fixed tuning set of graphs of
 the benchmark's shapes at reduced size (R-MAT, uniform-random and road-like
 grid searches; R-MAT, uniform-random and mixed multi-source batches), and
 writes the winner to ``tuned/<arch>_<CUs>cu.json``.  The binding applies that file when it loads
@@ -42,9 +43,13 @@ SPACE: Dict[str, List[int]] = {
     "batch_beta": [6, 12, 18, 36, 72],
     "small_frontier": [0, 4096, 16384, 32768, 131072],
     "lds_bitmap": [0, 1],
+    "blocks_per_cu": [1, 2],
+    "bu_mapping": [0, 1],
+    "batch_words": [1, 2, 4],
 }
-ORDER = ["block", "alpha", "beta", "hub_degree", "chunk_edges", "small_frontier", "lds_bitmap",
-         "batch_alpha", "batch_beta", "mode", "graph_chunk"]
+ORDER = ["block", "blocks_per_cu", "alpha", "beta", "hub_degree", "chunk_edges", "small_frontier",
+         "lds_bitmap", "bu_mapping", "batch_alpha", "batch_beta", "batch_words", "mode",
+         "graph_chunk"]
 
 # Tuning set: the benchmark's graph shapes at reduced size, other seeds.
 TUNING_SET = [
@@ -54,6 +59,7 @@ TUNING_SET = [
     {"kind": "batch", "graphs": [("rmat", 21, 7001)], "lanes": 64},
     {"kind": "batch", "graphs": [("urand", 21, 7002)], "lanes": 64},
     {"kind": "batch", "graphs": [("rmat", s, 7100 + s) for s in (14, 15, 16, 17, 18)], "lanes": 16},
+    {"kind": "batch", "graphs": [("rmat", 20, 7020)], "lanes": 256},
 ]
 
 
@@ -126,11 +132,11 @@ class _Bench:
                 if key not in self.graphs:
                     el = pool_edges(*key)
                     self.graphs[key] = gb.build_csr(el.n, el.src, el.dst)
-                    self.sources[key] = [int(x) for x in inputs.pick_sources(el, 64, seed=key[2] + 1)]
+                    self.sources[key] = [int(x) for x in inputs.pick_sources(el, 256, seed=key[2] + 1)]
             self.items.append(it)
         nmax = max(g.n for g in self.graphs.values())
         self.buf = [(torch.empty(nmax, dtype=torch.int32, device="cuda"),
-                     torch.empty(nmax, dtype=torch.int32, device="cuda")) for _ in range(80)]
+                     torch.empty(nmax, dtype=torch.int32, device="cuda")) for _ in range(256)]
         self.stream = torch.cuda.current_stream()
 
     def _time(self, fn) -> float:

@@ -198,6 +198,7 @@ static gap_params default_params() {
   p.small_frontier = 32768;
   p.lds_bitmap = 1;
   p.bu_mapping = 0;
+  p.batch_words = 4;
   p.serve_window_us = 5000;
   return p;
 }
@@ -252,6 +253,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.lds_bitmap != 0 && p.lds_bitmap != 1) {
     set_error("params: lds_bitmap must be 0 or 1");
+    return GAP_EINVAL;
+  }
+  if (p.batch_words != 1 && p.batch_words != 2 && p.batch_words != 4) {
+    set_error("params: batch_words must be 1, 2 or 4");
     return GAP_EINVAL;
   }
   if (p.serve_window_us < 0) {
@@ -728,6 +733,15 @@ gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          const int32_t *graph_of_source, const int32_t *sources,
                          int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
                          void *stream) {
+  return gap_bfs_batch_ex(graphs, num_graphs, graph_of_source, sources, num_sources, parents,
+                          depths, stream, nullptr, 0, nullptr);
+}
+
+gap_status gap_bfs_batch_ex(const gap_graph *const *graphs, int32_t num_graphs,
+                            const int32_t *graph_of_source, const int32_t *sources,
+                            int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
+                            void *stream, gap_level_stat *stats, int32_t max_levels,
+                            int32_t *num_levels) {
   clear_error();
   if (!graphs || !graph_of_source || !sources || !parents) {
     set_error("gap_bfs_batch: NULL array");
@@ -767,7 +781,7 @@ gap_status gap_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
     }
   }
   return run_bfs_batch(graphs, num_graphs, graph_of_source, sources, num_sources, parents, depths,
-                       (hipStream_t)stream, params_current());
+                       (hipStream_t)stream, params_current(), stats, max_levels, num_levels);
 }
 
 void gap_free(gap_graph *g) {
@@ -779,6 +793,8 @@ void gap_free(gap_graph *g) {
   if (g->row_ptr) (void)hipFree(g->row_ptr);
   if (g->col) (void)hipFree(g->col);
   if (g->wt) (void)hipFree(g->wt);
+  if (g->head_in && g->head_in != g->head) (void)hipFree(g->head_in);
+  if (g->head) (void)hipFree(g->head);
   delete g;
 }
 

@@ -518,7 +518,8 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
     if (st != GAP_OK) return st;
   }
   SearchArgs a{};
-  a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->n, g->nnz, g->directed};
+  a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->head_in, g->n, g->nnz,
+                 g->directed};
   a.parent = parent;
   a.depth = depth ? depth : ws->depth_scratch;
   a.source = source;
@@ -696,7 +697,8 @@ gap_status run_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent, 
   st = noalloc_base(g->device, stream, &base);
   if (st != GAP_OK) return st;
   SearchArgs a{};
-  a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->n, g->nnz, g->directed};
+  a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->head_in, g->n, g->nnz,
+                 g->directed};
   a.parent = parent;
   a.depth = depth ? depth : reinterpret_cast<int32_t *>(base + L.depth);
   a.source = source;

@@ -587,7 +587,9 @@ __device__ inline int nth_set_bit(uint64_t x, uint32_t k) {
 // Workgroup b owns the contiguous words [wlo, whi) of the vertex range and
 // hands them to its waves kBuChunk words at a time (an LDS cursor).  A lane
 // holds J vertices at once; every round reads four list entries of each held
-// vertex (one 16-byte load) and probes the frontier bitmap for them; a vertex
+// vertex (one 16-byte load: the vertex's head record in its first round, so
+// that vertices handed out in order read consecutive records, then the
+// column array) and probes the frontier bitmap for them; a vertex
 // that found its parent (its first frontier neighbour in list order) or ran
 // out of entries frees its slot, and the wave refills free slots from its
 // chunk before the next round.  So lanes do not idle while a wave's slowest
@@ -631,12 +633,14 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
   int64_t e[J];    // next list entry
   int32_t rem[J];  // entries left
   int32_t deg[J];  // list length (the frontier-edge count of an undirected find)
+  bool fresh[J];   // the first four entries are read from the vertex's head record
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     v[j] = -1;
     e[j] = 0;
     rem[j] = 0;
     deg[j] = 0;
+    fresh[j] = false;
   }
   uint64_t win = 0ull;  // this lane's word of the chunk: unvisited bits not yet handed out
   int64_t wbase = 0;    // first word of the chunk (wave-uniform)
@@ -697,6 +701,7 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
           e[j] = rp[vv];
           rem[j] = (int32_t)(rp[vv + 1] - e[j]);
           deg[j] = rem[j];
+          fresh[j] = true;
           if (STATS) acc.unvisited += 1;
         }
       }
@@ -714,7 +719,10 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       i32x4_a4 w = {-1, -1, -1, -1};
-      if (v[j] >= 0) w = *reinterpret_cast<const i32x4_a4 *>(col + e[j]);
+      if (v[j] >= 0)
+        w = *reinterpret_cast<const i32x4_a4 *>(fresh[j] ? reinterpret_cast<const int32_t *>(a.g.head_in + v[j])
+                                                         : col + e[j]);
+      fresh[j] = false;
 #pragma unroll
       for (int k = 0; k < 4; ++k) u[j][k] = (v[j] >= 0 && k < rem[j]) ? w[k] : -1;
     }

@@ -271,6 +271,36 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int
   return GAP_OK;
 }
 
+// head[v] = the first four entries of v's list (-1 past its end).
+__global__ __launch_bounds__(256) void k_make_head(const int64_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, int64_t n,
+                                                   int4 *__restrict__ head) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+    int4 h;
+    h.x = b + 0 < e ? col[b + 0] : -1;
+    h.y = b + 1 < e ? col[b + 1] : -1;
+    h.z = b + 2 < e ? col[b + 2] : -1;
+    h.w = b + 3 < e ? col[b + 3] : -1;
+    head[v] = h;
+  }
+}
+
+static gap_status make_head(const int64_t *row_ptr, const int32_t *col, int64_t n,
+                            hipStream_t stream, int4 **out) {
+  *out = nullptr;
+  GAP_HIP(hipMalloc(out, sizeof(int4) * (size_t)n));
+  k_make_head<<<grid_for(n), 256, 0, stream>>>(row_ptr, col, n, *out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipFree(*out);
+    *out = nullptr;
+    return hip_fail(e, "k_make_head");
+  }
+  return GAP_OK;
+}
+
 gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                      const int32_t *weights, bool directed, hipStream_t stream, gap_graph **out) {
   int dev = 0;
@@ -331,6 +361,26 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
     g->row_ptr_in = g->row_ptr;
     g->col_in = g->col;
     g->nnz_in = g->nnz;
+  }
+  g->head = g->head_in = nullptr;
+  st = make_head(g->row_ptr, g->col, n, stream, &g->head);
+  if (st == GAP_OK) {
+    if (directed)
+      st = make_head(g->row_ptr_in, g->col_in, n, stream, &g->head_in);
+    else
+      g->head_in = g->head;
+  }
+  if (st != GAP_OK) {
+    if (g->head) (void)hipFree(g->head);
+    if (directed) {
+      (void)hipFree(g->row_ptr_in);
+      (void)hipFree(g->col_in);
+    }
+    (void)hipFree(g->row_ptr);
+    (void)hipFree(g->col);
+    if (g->wt) (void)hipFree(g->wt);
+    delete g;
+    return st;
   }
   *out = g;
   return GAP_OK;

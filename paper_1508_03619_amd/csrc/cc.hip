@@ -54,13 +54,14 @@ constexpr int kSample = 1024;
 // as its own root and is hooked under its first list entry (the smallest
 // neighbour, lists being ascending) when that is smaller.  No other thread
 // writes parent[v] here, and parents only decrease, so no cycle forms.
-__global__ __launch_bounds__(kCcBlock) void k_cc_init(int64_t n, const int64_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ col,
+// The first entries come from the graph's 16-byte head records (read in
+// vertex order), not from one line of the column array per vertex.
+__global__ __launch_bounds__(kCcBlock) void k_cc_init(int64_t n, const int4 *__restrict__ head,
                                                       int32_t *__restrict__ parent) {
   for (int64_t v = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * kCcBlock) {
-    const int64_t beg = rp[v];
-    const int32_t first = rp[v + 1] > beg ? col[beg] : (int32_t)v;
+    const int32_t h = head[v].x;
+    const int32_t first = h >= 0 ? h : (int32_t)v;
     parent[v] = first < (int32_t)v ? first : (int32_t)v;
   }
 }
@@ -117,14 +118,19 @@ struct CcArgs {
 // is a local minimum and is left for its neighbours to find).
 __global__ __launch_bounds__(kCcBlock) void k_cc_sample(int64_t n, const int64_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
+                                                        const int4 *__restrict__ head,
                                                         int32_t *parent, int r) {
   for (int64_t u = blockIdx.x * (int64_t)kCcBlock + threadIdx.x; u < n;
        u += (int64_t)gridDim.x * kCcBlock) {
-    const int64_t beg = rp[u], deg = rp[u + 1] - beg;
-    if (r < deg) {
-      const int32_t v = col[beg + r];
-      if (v < u) link_sample(parent, (int32_t)u, v);
+    int32_t v = -1;
+    if (r < 4) {  // in the head record (-1 past the list's end)
+      const int4 h = head[u];
+      v = r == 1 ? h.y : (r == 2 ? h.z : h.w);
+    } else {
+      const int64_t beg = rp[u], deg = rp[u + 1] - beg;
+      if (r < deg) v = col[beg + r];
     }
+    if (v >= 0 && v < u) link_sample(parent, (int32_t)u, v);
   }
 }
 
@@ -264,10 +270,10 @@ gap_status run_cc(const gap_graph *g, int32_t *labels, hipStream_t stream) {
   int2 *items = carve<int2>(p, cap_items);
   const int grid = di->cus * 8;
   const int64_t n = g->n;
-  k_cc_init<<<grid, kCcBlock, 0, stream>>>(n, g->row_ptr, g->col, labels);
+  k_cc_init<<<grid, kCcBlock, 0, stream>>>(n, g->head, labels);
   k_cc_compress<<<grid, kCcBlock, 0, stream>>>(n, labels);
   for (int r = 1; r < kSampleRounds; ++r) {
-    k_cc_sample<<<grid, kCcBlock, 0, stream>>>(n, g->row_ptr, g->col, labels, r);
+    k_cc_sample<<<grid, kCcBlock, 0, stream>>>(n, g->row_ptr, g->col, g->head, labels, r);
     k_cc_compress<<<grid, kCcBlock, 0, stream>>>(n, labels);
   }
   k_cc_pick<<<1, kSample, 0, stream>>>(n, labels, giant, nitems);

@@ -33,6 +33,7 @@ struct DevGraph {
   const int32_t *col;         // int32[nnz], each row ascending
   const int64_t *row_ptr_in;  // in-lists (bottom-up); the same arrays when undirected
   const int32_t *col_in;
+  const int4 *head_in;        // first four in-list entries of every vertex (-1 past the end)
   int64_t n;
   int64_t nnz;
   int32_t directed;
@@ -355,10 +356,13 @@ __device__ inline bool grid_sync(Ctl *ctl, unsigned int nblocks, const Totals &p
 
 // A parked workgroup waits until the small group sets ctl->resume above
 // `level`, then takes over the handed-on state.  The wait is bounded by the
-// time without progress, not by its total length: every release of the
-// small group's barrier (one per small level) restarts the clock, so a
-// search of millions of small levels in a row never trips it, while a small
-// group that stops making progress is caught after `limit` ticks.
+// time without progress, not by its total length: whenever `limit` ticks
+// have passed, the small group's generation word is compared with its value
+// at the previous check, and the clock restarts if the small group finished
+// a level meanwhile.  So a search of millions of small levels in a row never
+// trips it, a small group that stops making progress is caught within
+// 2 * `limit` ticks, and the parked workgroups poll only `resume` and the
+// error word in between, not the small barrier's release flag.
 constexpr uint64_t kParkTimeoutTicks = 1000000000ull;  // ~10 s at 100 MHz
 
 __device__ inline bool park_wait(Ctl *ctl, unsigned int level, ParkState &ps, uint64_t limit) {
@@ -375,16 +379,18 @@ __device__ inline bool park_wait(Ctl *ctl, unsigned int level, ParkState &ps, ui
         ok = 0;
         break;
       }
-      const unsigned int g = ld_agent(&ctl->sgen[0].gen);
       const uint64_t now = rt_clock();
-      if (g != seen) {  // the small group finished another level
-        seen = g;
-        t0 = now;
-      } else if (now - t0 > limit) {
-        __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
+      if (now - t0 > limit) {
+        const unsigned int g = ld_agent(&ctl->sgen[0].gen);
+        if (g != seen) {  // the small group finished a level within the last bound
+          seen = g;
+          t0 = now;
+        } else {
+          __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

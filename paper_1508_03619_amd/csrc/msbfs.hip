@@ -48,6 +48,7 @@ constexpr int kMsTraceLevels = 128;
 struct MsSeg {
   const int64_t *row_ptr;
   const int32_t *col;
+  const int4 *head;   // first four entries of every list (-1 past the end)
   int64_t n;          // vertices of the graph
   int64_t vbase;      // first virtual vertex (multiple of 64)
   int32_t lane_base;  // first lane (index into the output tables)
@@ -66,8 +67,12 @@ struct MsCtl {
   Ctl base;                        // grid barrier, queue segment counters
   MsSegTotals tot[2][kMaxSeg];     // level parity x segment
   // per level: real-time stamps (advance start, step start, step end),
-  // direction / frontier vertices / frontier edges of segment 0
+  // direction of segment 0, frontier vertices and frontier edges (segment
+  // 0; with statistics, every segment)
   unsigned long long trace[kMsTraceLevels][6];
+  // with statistics, per level: vertices a bottom-up step searched for (some
+  // lane needed them) and the adjacency entries it read
+  unsigned long long lvstat[kMsTraceLevels][2];
 };
 
 struct MsArgs {
@@ -92,6 +97,7 @@ struct MsShared {
   int64_t n[kMaxSeg];
   const int64_t *row_ptr[kMaxSeg];
   const int32_t *col[kMaxSeg];
+  const int4 *head[kMaxSeg];
   int32_t lane_base[kMaxSeg];
   int32_t lanes[kMaxSeg];
   int32_t dir[kMaxSeg];
@@ -166,7 +172,7 @@ __device__ inline uint64_t wave_excl_or_u64(uint64_t x) {
 
 // ---- the persistent kernel ---------------------------------------------------------
 
-template <int W>
+template <int W, bool STATS>
 __device__ __forceinline__ void msbfs(const MsArgs &a) {
   __shared__ MsShared<W> sh;
   const int64_t nthreads = (int64_t)gridDim.x * kMsBlock;
@@ -184,6 +190,7 @@ __device__ __forceinline__ void msbfs(const MsArgs &a) {
     sh.n[s] = a.segs[s].n;
     sh.row_ptr[s] = a.segs[s].row_ptr;
     sh.col[s] = a.segs[s].col;
+    sh.head[s] = a.segs[s].head;
     sh.lane_base[s] = a.segs[s].lane_base;
     sh.lanes[s] = a.segs[s].lanes;
     sh.dir[s] = kTopDown;
@@ -321,9 +328,18 @@ __device__ __forceinline__ void msbfs(const MsArgs &a) {
     if (tracer && d < kMsTraceLevels) {
       a.ctl->trace[d][1] = rt_clock();
       a.ctl->trace[d][3] = (unsigned long long)sh.dir[0];
-      a.ctl->trace[d][4] = (unsigned long long)sh.nf_prev[0];
-      a.ctl->trace[d][5] = ld_agent(&a.ctl->tot[d & 1][0].mf);
+      unsigned long long nf = (unsigned long long)sh.nf_prev[0];
+      unsigned long long mf = ld_agent(&a.ctl->tot[d & 1][0].mf);
+      if (STATS) {
+        for (int s = 1; s < nseg; ++s) {
+          nf += (unsigned long long)sh.nf_prev[s];
+          mf += ld_agent(&a.ctl->tot[d & 1][s].mf);
+        }
+      }
+      a.ctl->trace[d][4] = nf;
+      a.ctl->trace[d][5] = mf;
     }
+    unsigned long long st_u = 0, st_scan = 0;  // statistics of this thread's bottom-up work
 
     // ---- step -------------------------------------------------------------------
     StepArgs qa{};
@@ -381,9 +397,11 @@ __device__ __forceinline__ void msbfs(const MsArgs &a) {
                       ~ld_agent((const unsigned long long *)&N[xv * W + w]);
             left |= need[w] != 0ull;
           }
+          if (STATS && lane == 0 && k == 0 && left) st_u += 1;
           for (int64_t e0 = beg; e0 < end && left; e0 += kWave) {
             const int64_t e = e0 + lane;
             const int32_t ul = e < end ? sh.col[s][e] : -1;
+            if (STATS && ul >= 0) st_scan += 1;
             left = false;
 #pragma unroll
             for (int w = 0; w < W; ++w) {
@@ -486,10 +504,23 @@ __device__ __forceinline__ void msbfs(const MsArgs &a) {
       // a lane whose vertex is settled or exhausted just contributes nothing
       bool act = want;
       int64_t e = beg;
+      if (STATS && want && end > beg) st_u += 1;
+      bool first = true;  // the first four entries come from the head record
       while (__ballot(act) != 0ull) {
+        if (STATS && act) st_scan += (unsigned long long)(end - e < 4 ? end - e : 4);
         int32_t ul[4];
+        if (first) {
+          int4 h = make_int4(-1, -1, -1, -1);
+          if (act) h = sh.head[s][vl];
+          ul[0] = h.x;
+          ul[1] = h.y;
+          ul[2] = h.z;
+          ul[3] = h.w;
+          first = false;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) ul[k] = (act && e + k < end) ? sh.col[s][e + k] : -1;
+          for (int k = 0; k < 4; ++k) ul[k] = (act && e + k < end) ? sh.col[s][e + k] : -1;
+        }
         uint64_t fu[4][W];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -536,15 +567,22 @@ __device__ __forceinline__ void msbfs(const MsArgs &a) {
         }
       }
     }
+    if (STATS && d < kMsTraceLevels) {
+      const unsigned long long wu = wave_sum_u64(st_u), ws = wave_sum_u64(st_scan);
+      if (lane == 0 && (wu | ws)) {
+        add_agent(&a.ctl->lvstat[d][0], wu);
+        add_agent(&a.ctl->lvstat[d][1], ws);
+      }
+    }
     if (!grid_sync(ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
     if (tracer && d < kMsTraceLevels) a.ctl->trace[d][2] = rt_clock();
     swap_ptr(F, N);
   }
 }
 
-template <int W>
+template <int W, bool STATS>
 __global__ __launch_bounds__(kMsBlock) void k_msbfs(MsArgs a) {
-  msbfs<W>(a);
+  msbfs<W, STATS>(a);
   note_error(a.sticky, &a.ctl->base);
 }
 
@@ -594,9 +632,9 @@ __global__ __launch_bounds__(kOutBlock) void k_ms_output(MsArgs a, int64_t nword
 // ---- host side ------------------------------------------------------------------------
 
 template <int W>
-static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int split, int64_t ntiles,
+static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int split, bool stats, int64_t ntiles,
                             const int64_t *tile_base, hipStream_t stream) {
-  auto kern = k_msbfs<W>;
+  auto kern = stats ? k_msbfs<W, true> : k_msbfs<W, false>;
   int per_cu = 0;
   GAP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMsBlock, 0));
   if (per_cu < 1) {
@@ -622,8 +660,10 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          const int32_t *graph_of_source, const int32_t *sources,
                          int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
-                         hipStream_t stream, const gap_params &p) {
+                         hipStream_t stream, const gap_params &p, gap_level_stat *stats,
+                         int32_t max_levels, int32_t *num_levels) {
   const int dev = graphs[0]->device;
+  const bool want_stats = stats != nullptr && max_levels > 0;
   const DeviceInfo *di = nullptr;
   gap_status st = device_info(dev, &di);
   if (st != GAP_OK) return st;
@@ -634,7 +674,8 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
   for (int32_t i = 0; i < num_sources; ++i) by_graph[(size_t)graph_of_source[i]].push_back(i);
   size_t maxl = 1;
   for (auto &v : by_graph) maxl = std::max(maxl, v.size());
-  const int W = maxl <= 64 ? 1 : (maxl <= 128 ? 2 : 4);
+  const int Wneed = maxl <= 64 ? 1 : (maxl <= 128 ? 2 : 4);
+  const int W = std::min(Wneed, (int)p.batch_words);
   const int lanes_per_seg = 64 * W;
 
   std::vector<MsSeg> segs;
@@ -648,6 +689,7 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
       MsSeg s;
       s.row_ptr = graphs[g]->row_ptr;
       s.col = graphs[g]->col;
+      s.head = graphs[g]->head;
       s.n = graphs[g]->n;
       s.vbase = nvirt;
       s.lane_base = (int32_t)lane_src.size();
@@ -756,13 +798,46 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
   st = coop_begin(dev, stream, p.grid_split, &order);
   if (st != GAP_OK) return st;
   switch (W) {
-    case 1: st = launch_ms<1>(a, di, p.grid_split, ntiles, d_tile_base, stream); break;
-    case 2: st = launch_ms<2>(a, di, p.grid_split, ntiles, d_tile_base, stream); break;
-    default: st = launch_ms<4>(a, di, p.grid_split, ntiles, d_tile_base, stream); break;
+    case 1: st = launch_ms<1>(a, di, p.grid_split, want_stats, ntiles, d_tile_base, stream); break;
+    case 2: st = launch_ms<2>(a, di, p.grid_split, want_stats, ntiles, d_tile_base, stream); break;
+    default: st = launch_ms<4>(a, di, p.grid_split, want_stats, ntiles, d_tile_base, stream); break;
   }
   gap_status st2 = coop_end(dev, stream, &order);
   if (st != GAP_OK) return st;
   if (st2 != GAP_OK) return st2;
+  if (want_stats) {
+    GAP_HIP(hipStreamSynchronize(stream));
+    int err = 0;
+    GAP_HIP(hipMemcpy(&err, &a.ctl->base.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err != 0) {
+      set_error(err == GAP_ETIMEOUT ? "device-side wait timed out (grid barrier)"
+                                    : "batch ran more levels than vertices");
+      return err;
+    }
+    static_assert(offsetof(MsCtl, lvstat) == offsetof(MsCtl, trace) +
+                                                 sizeof(unsigned long long) * kMsTraceLevels * 6,
+                  "trace and lvstat are copied together");
+    std::vector<unsigned long long> tr((size_t)kMsTraceLevels * 8);
+    GAP_HIP(hipMemcpy(tr.data(), reinterpret_cast<char *>(a.ctl) + offsetof(MsCtl, trace),
+                      tr.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    const unsigned long long *T = tr.data();
+    const unsigned long long *LS = tr.data() + (size_t)kMsTraceLevels * 6;
+    int levels = 0;
+    while (levels < kMsTraceLevels && T[levels * 6 + 2] != 0ull) ++levels;
+    const int nrec = std::min(levels, max_levels);
+    for (int d = 0; d < nrec; ++d) {
+      gap_level_stat &r = stats[d];
+      r.level = d;
+      r.direction = (int32_t)T[d * 6 + 3];
+      r.frontier = (int64_t)T[d * 6 + 4];
+      r.frontier_edges = (int64_t)T[d * 6 + 5];
+      r.claimed = d + 1 < levels ? (int64_t)T[(d + 1) * 6 + 4] : 0;
+      r.unvisited = r.direction == kBottomUp ? (int64_t)LS[d * 2 + 0] : 0;
+      r.scanned = r.direction == kBottomUp ? (int64_t)LS[d * 2 + 1] : r.frontier_edges;
+      r.time_ns = T[d * 6 + 2] > T[d * 6 + 0] ? (int64_t)((T[d * 6 + 2] - T[d * 6 + 0]) * 10ull) : 0;
+    }
+    if (num_levels) *num_levels = levels;
+  }
   if (getenv("GAP_MS_TRACE")) {  // development aid: per-level timing of segment 0
     GAP_HIP(hipStreamSynchronize(stream));
     static unsigned long long tr[kMsTraceLevels][6];

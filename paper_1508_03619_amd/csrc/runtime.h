@@ -25,6 +25,12 @@ struct gap_graph {
   int64_t max_degree;
   int32_t *wt;          // device int32[nnz] out-list weights, or NULL (every weight 1)
   int32_t max_weight;   // 1 when unweighted
+  // First four entries of every list, one 16-byte record per vertex (-1 past
+  // the list's end): a search's first read of a list, and the components'
+  // sampling, read these records in vertex order instead of one line of
+  // `col` per vertex.  head_in == head when undirected.
+  int4 *head;           // device int4[n], out-lists
+  int4 *head_in;        // device int4[n], in-lists
 };
 
 namespace gap {
@@ -183,7 +189,8 @@ gap_status noalloc_status(hipStream_t stream);
 gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
                          const int32_t *graph_of_source, const int32_t *sources,
                          int32_t num_sources, int32_t *const *parents, int32_t *const *depths,
-                         hipStream_t stream, const gap_params &p);
+                         hipStream_t stream, const gap_params &p, gap_level_stat *stats,
+                         int32_t max_levels, int32_t *num_levels);
 // Implemented in bc.hip
 gap_status run_bc(const gap_graph *g, const int32_t *sources, int32_t num_sources, double *score,
                   bool normalise, hipStream_t stream);

@@ -40,7 +40,8 @@ class _Params(ctypes.Structure):
                 ("batch_alpha", ctypes.c_int32), ("batch_beta", ctypes.c_int32),
                 ("grid_split", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
                 ("lds_bitmap", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32),
-                ("bu_mapping", ctypes.c_int32), ("serve_window_us", ctypes.c_int32)]
+                ("bu_mapping", ctypes.c_int32), ("batch_words", ctypes.c_int32),
+                ("serve_window_us", ctypes.c_int32)]
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_]
@@ -65,7 +66,7 @@ EXPORTED = ["gap_build_csr", "gap_graph_info", "gap_graph_directed", "gap_graph_
             "gap_free", "gap_last_error", "gap_set_params", "gap_get_params", "gap_bfs_ex",
             "gap_device_query", "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
             "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc", "gap_stream_status",
-            "gap_shutdown", "gap_bfs_noalloc", "gap_serve_open", "gap_serve_submit",
+            "gap_shutdown", "gap_bfs_noalloc", "gap_bfs_batch_ex", "gap_serve_open", "gap_serve_submit",
             "gap_serve_poll", "gap_serve_close"]
 
 
@@ -105,6 +106,9 @@ def load():
                                  ctypes.POINTER(LevelStat), i32, i32p]
         L.gap_bfs_batch.argtypes = [ctypes.POINTER(vp), i32, i32p, i32p, i32,
                                     ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.gap_bfs_batch_ex.argtypes = [ctypes.POINTER(vp), i32, i32p, i32p, i32,
+                                       ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                       ctypes.POINTER(LevelStat), i32, i32p]
         L.gap_free.argtypes = [vp]
         L.gap_free.restype = None
         L.gap_last_error.argtypes = []
@@ -124,7 +128,7 @@ def load():
         L.gap_shutdown.argtypes = []
         L.gap_shutdown.restype = None
         for name in ("gap_build_csr", "gap_graph_info", "gap_graph_export", "gap_graph_export_in",
-                     "gap_graph_directed", "gap_bfs", "gap_bfs_ex", "gap_bfs_noalloc",
+                     "gap_graph_directed", "gap_bfs", "gap_bfs_ex", "gap_bfs_noalloc", "gap_bfs_batch_ex",
                      "gap_bfs_batch", "gap_set_params", "gap_get_params", "gap_device_query",
                      "gap_stream_copy", "gap_bc", "gap_build_csr_weighted",
                      "gap_graph_export_weights", "gap_sssp", "gap_sssp_ex", "gap_cc",
@@ -417,8 +421,11 @@ class Server:
 
 
 def bfs_batch(graphs: Sequence[Graph], graph_of_source: Sequence[int], sources: Sequence[int],
-              parents: Sequence, depths: Optional[Sequence] = None, stream=None):
-    """Lane i searches graphs[graph_of_source[i]] from sources[i]."""
+              parents: Sequence, depths: Optional[Sequence] = None, stream=None,
+              stats: bool = False, max_levels: int = 128):
+    """Lane i searches graphs[graph_of_source[i]] from sources[i].  With
+    stats=True the call waits for the batch and returns per-level records
+    (gap_bfs_batch_ex)."""
     L = load()
     ng, ns = len(graphs), len(sources)
     gh = (ctypes.c_void_p * ng)(*[g.handle.value for g in graphs])
@@ -434,7 +441,15 @@ def bfs_batch(graphs: Sequence[Graph], graph_of_source: Sequence[int], sources: 
     da = None
     if depths is not None:
         da = (ctypes.c_void_p * ns)(*[_ptr(t) for t in depths])
+    if stats:
+        recs = (LevelStat * max_levels)()
+        nl = ctypes.c_int32(0)
+        _check(L.gap_bfs_batch_ex(gh, ng, _i32p(gos), _i32p(src), ns, pa, da, _stream_handle(stream),
+                                  recs, int(max_levels), ctypes.byref(nl)))
+        return [{k: int(getattr(recs[i], k)) for k, _ in LevelStat._fields_}
+                for i in range(min(nl.value, max_levels))]
     _check(L.gap_bfs_batch(gh, ng, _i32p(gos), _i32p(src), ns, pa, da, _stream_handle(stream)))
+    return None
 
 
 BC_RAW = 1  # gap_bc flag

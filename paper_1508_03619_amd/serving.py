@@ -82,6 +82,7 @@ class Scheduler:
         self.max_lanes = int(max_lanes)
         self.used = 0
         self.peak_used = 0
+        self.admission_waits = 0  # walks stopped by a query that did not fit
         self._order: collections.deque = collections.deque()   # qids in arrival order
         self._by_graph: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
         self._live: Dict[int, Query] = {}                       # waiting queries
@@ -123,6 +124,32 @@ class Scheduler:
             batch.append(q)
         self.peak_used = max(self.peak_used, self.used)
         return batch
+
+    def start_each(self, start: Callable[[Query], bool]) -> int:
+        """Continuous batching: walks the waiting queries in arrival order and
+        calls ``start(q)`` for each one whose outputs fit the budget; a query
+        that ``start`` takes is charged and leaves the queue.  A query that
+        does not fit stops the walk (nothing overtakes it on memory); one that
+        ``start`` refuses (no room for its graph now) is passed over.
+        Returns the number of queries started."""
+        started = 0
+        for qid in list(self._order):
+            q = self._live.get(qid)
+            if q is None:
+                continue
+            c = self.cost(q)
+            if self.used + c > self.budget:
+                self.admission_waits += 1
+                break
+            if start(q):
+                self.used += c
+                self.peak_used = max(self.peak_used, self.used)
+                del self._live[qid]
+                self._by_graph[q.graph].remove(q)
+                started += 1
+        while self._order and self._order[0] not in self._live:
+            self._order.popleft()
+        return started
 
     def release(self, batch: Sequence[Query]) -> None:
         for q in batch:
@@ -233,6 +260,40 @@ def serve(ex, sched: Scheduler, queries, on_done: Optional[Callable] = None) -> 
                 q.batch_size = len(batch)
             ex.launch(slot, batch)
             inflight[slot] = batch
+            progressed = True
+        if not progressed:
+            ex.idle(src.next_time())
+    return finished
+
+
+def serve_continuous(ex, sched: Scheduler, queries, on_done: Optional[Callable] = None) -> List[Query]:
+    """Continuous batching: every admitted query starts as soon as the
+    executor can take it (``ex.try_start``: it joins a running search of its
+    graph at the next level boundary, or starts on an idle slot) and
+    completes on its own (``ex.poll_done``).  Same arrival sources and
+    budget accounting as ``serve``."""
+    src = queries if hasattr(queries, "due") else OpenArrivals(queries)
+    finished: List[Query] = []
+    inflight = 0
+    ex.start()
+    while not src.exhausted or sched.pending or inflight:
+        progressed = False
+        now = ex.now()
+        for q in src.due(now):
+            sched.submit(q)
+            progressed = True
+        for q, outs in ex.poll_done():
+            q.done = ex.now()
+            sched.release([q])
+            inflight -= 1
+            finished.append(q)
+            src.completed(q, q.done)
+            if on_done is not None:
+                on_done([q], outs)
+            progressed = True
+        started = sched.start_each(lambda q: ex.try_start(q, ex.now()))
+        if started:
+            inflight += started
             progressed = True
         if not progressed:
             ex.idle(src.next_time())
@@ -474,6 +535,205 @@ class GpuExecutor:
             wait = next_arrival - self.now()
             if wait > 2e-4:
                 time.sleep(min(wait, 1e-3) * 0.5)
+
+
+class SimContinuous:
+    """Simulated device for host tests of ``serve_continuous``: ``slots``
+    servers of ``lanes`` lanes; a query joining a server runs for
+    ``service(n)`` seconds from its start (lanes are independent), and a
+    server is bound to one graph while it holds queries."""
+
+    def __init__(self, slots: int, lanes: int, service: Callable[[int], float], sizes: Sequence[int]):
+        self.slots, self.lanes, self.service, self.sizes = slots, lanes, service, list(sizes)
+        self.t = 0.0
+        self.bound: List[Optional[int]] = [None] * slots
+        self.held: List[Dict[int, tuple]] = [dict() for _ in range(slots)]
+        self.max_lanes_used = 0
+        self.joined_running = 0
+
+    def start(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def try_start(self, q: Query, t: float) -> bool:
+        order = [s for s in range(self.slots) if self.bound[s] == q.graph] + \
+                [s for s in range(self.slots) if not self.held[s]]
+        for s in order:
+            if len(self.held[s]) >= self.lanes:
+                continue
+            if self.held[s]:
+                self.joined_running += 1
+            self.bound[s] = q.graph
+            q.start = t
+            q.batch_size = len(self.held[s]) + 1
+            self.held[s][q.qid] = (q, t + self.service(self.sizes[q.graph]))
+            self.max_lanes_used = max(self.max_lanes_used, len(self.held[s]))
+            return True
+        return False
+
+    def poll_done(self):
+        out = []
+        for s in range(self.slots):
+            for qid, (q, end) in list(self.held[s].items()):
+                if end <= self.t:
+                    del self.held[s][qid]
+                    out.append((q, None))
+            if not self.held[s]:
+                self.bound[s] = None
+        return out
+
+    def idle(self, next_arrival: Optional[float]):
+        cands = [end for h in self.held for (_, end) in h.values()]
+        if next_arrival is not None:
+            cands.append(next_arrival)
+        if not cands:
+            raise RuntimeError("serving loop idle with nothing pending")
+        self.t = max(self.t, min(cands))
+
+
+class ContinuousExecutor:
+    """Continuous batching on the device: ``slots`` servers (gap_serve_*), one
+    HIP stream each, every one bound to one graph while it holds queries; a
+    query joins its graph's running search at the next level boundary (up to
+    ``lanes`` at once), or binds an idle server.  Graphs whose one-query
+    serving time is far above a single-source search (high diameter: a
+    serving level costs a dense pass over the vertices) run as single-source
+    searches on an idle slot instead (``calibrate``).  With grid_split =
+    slots every launch takes 1/slots of the compute units, so all slots run
+    at once."""
+
+    def __init__(self, graphs: Sequence, slots: int = 8, lanes: int = 64,
+                 sources: Optional[Sequence] = None):
+        import torch
+        from . import gapbfs as gb
+        self.torch, self.gb = torch, gb
+        self.graphs = list(graphs)
+        self.slots, self.lanes = int(slots), int(lanes)
+        self._saved_params = gb.get_params()
+        gb.set_params(grid_split=self.slots)
+        self.streams = [torch.cuda.Stream() for _ in range(self.slots)]
+        maxn = max(g.n for g in self.graphs)
+        maxe = max(g.nnz for g in self.graphs)
+        self.servers = [gb.Server(maxn, maxe, stream=st) for st in self.streams]
+        self.bound: List[Optional[int]] = [None] * self.slots
+        self.held: List[Dict[int, tuple]] = [dict() for _ in range(self.slots)]
+        self.single: Dict[int, tuple] = {}  # slot -> (query, parent, depth, event)
+        self.single_graphs: set = set()
+        self.t0 = 0.0
+        self.launch_kinds = collections.Counter()
+        self.t_single: Dict[int, float] = {}
+        self.t_serve: Dict[int, float] = {}
+        if sources is not None:
+            self.calibrate(sources)
+
+    def calibrate(self, sources: Sequence[np.ndarray], reps: int = 2):
+        """Per graph: one single-source search and one query through a
+        server (best of ``reps``, host clock); graphs whose served query takes
+        more than twice the single search run as single searches."""
+        torch, gb = self.torch, self.gb
+        st, srv = self.streams[0], self.servers[0]
+        for gi, g in enumerate(self.graphs):
+            s = int(sources[gi][0])
+            p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            best_single = best_serve = math.inf
+            for _ in range(reps + 1):
+                t = time.perf_counter()
+                gb.bfs(g, s, p, d, stream=st)
+                st.synchronize()
+                best_single = min(best_single, time.perf_counter() - t)
+                t = time.perf_counter()
+                if not srv.submit(g, -1, s, p, d):
+                    raise RuntimeError("calibration: the server refused a query")
+                deadline = time.perf_counter() + 30.0
+                while not srv.poll():
+                    if time.perf_counter() > deadline:
+                        raise RuntimeError("calibration: a served query did not complete in 30 s")
+                st.synchronize()
+                best_serve = min(best_serve, time.perf_counter() - t)
+            self.t_single[gi], self.t_serve[gi] = best_single, best_serve
+            if best_serve > 2.0 * best_single:
+                self.single_graphs.add(gi)
+            del p, d
+        gb.stream_status(st)
+
+    def start(self):
+        self.torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def _idle_slot(self) -> Optional[int]:
+        for s in range(self.slots):
+            if not self.held[s] and s not in self.single:
+                return s
+        return None
+
+    def try_start(self, q: Query, t: float) -> bool:
+        torch, gb = self.torch, self.gb
+        g = self.graphs[q.graph]
+        if q.graph in self.single_graphs:
+            s = self._idle_slot()
+            if s is None:
+                return False
+            p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            gb.bfs(g, q.source, p, d, stream=self.streams[s])
+            ev = torch.cuda.Event()
+            ev.record(self.streams[s])
+            self.single[s] = (q, p, d, ev)
+            q.start, q.batch_size = t, 1
+            self.launch_kinds["single"] += 1
+            return True
+        cands = [s for s in range(self.slots) if self.bound[s] == q.graph and len(self.held[s]) < self.lanes]
+        if not cands:
+            s = self._idle_slot()
+            if s is None:
+                return False
+            cands = [s]
+        s = cands[0]
+        p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        d = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        if not self.servers[s].submit(g, q.qid, q.source, p, d):
+            return False
+        self.launch_kinds["joined" if self.held[s] else "fresh"] += 1
+        self.bound[s] = q.graph
+        self.held[s][q.qid] = (q, p, d)
+        q.start, q.batch_size = t, len(self.held[s])
+        return True
+
+    def poll_done(self):
+        out = []
+        for s in range(self.slots):
+            if self.held[s]:
+                for qid in self.servers[s].poll():
+                    q, p, d = self.held[s].pop(qid)
+                    out.append((q, (p, d)))
+                if not self.held[s]:
+                    self.bound[s] = None
+            if s in self.single and self.single[s][3].query():
+                q, p, d, _ = self.single.pop(s)
+                out.append((q, (p, d)))
+        return out
+
+    def idle(self, next_arrival: Optional[float]):
+        if next_arrival is not None:
+            wait = next_arrival - self.now()
+            if wait > 2e-4:
+                time.sleep(min(wait, 1e-3) * 0.5)
+
+    def close(self):
+        """Wait for every slot, check the streams' status, release the servers
+        and restore the process-wide parameters."""
+        self.torch.cuda.synchronize()
+        for st in self.streams:
+            self.gb.stream_status(st)
+        for srv in self.servers:
+            srv.close()
+        self.gb.set_params(**self._saved_params)
 
 
 # ---------------------------------------------------------------------------

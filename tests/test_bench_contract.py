@@ -43,3 +43,21 @@ def test_algorithmic_bytes_model():
     want_td2 = 20 * 30 + n // 8 + 20 * 30 + 8 * 60 + 12 * 5
     assert bench.algorithmic_bytes([td, bu, td2], n) == (base + 20 * 10 + 8 * 100 + 12 * 40 + want_bu
                                                         + want_td2)
+
+
+def test_batch_algorithmic_bytes_model():
+    """The multi-source byte model, term by term (64 lanes: W = 1; 100
+    lanes: W = 2)."""
+    import bench
+    n = 1000
+    for lanes, W in ((64, 1), (100, 2)):
+        base = 24 * W * n + 8 * lanes * n
+        assert bench.batch_algorithmic_bytes([], n, lanes) == base
+        td = {"direction": 1, "frontier": 10, "frontier_edges": 100, "claimed": 40,
+              "scanned": 100, "unvisited": 0}
+        want_td = 24 * W * n + 8 * W * 10 + 16 * 10 + 100 * (4 + 8 * W)
+        assert bench.batch_algorithmic_bytes([td], n, lanes) == base + want_td
+        bu = {"direction": 2, "frontier": 40, "frontier_edges": 400, "claimed": 300,
+              "scanned": 900, "unvisited": 500}
+        want_bu = 24 * W * n + 16 * 500 + 16 * W * 500 + 900 * (4 + 8 * W)
+        assert bench.batch_algorithmic_bytes([td, bu], n, lanes) == base + want_td + want_bu

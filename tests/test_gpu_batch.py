@@ -133,3 +133,40 @@ def test_batch_grid_high_diameter(gpu):
     say("grid batch of 70")
     P, D = run_batch(gpu, [g], [0] * 70, srcs)
     check_lanes([A], [0] * 70, srcs, P, D, "grid")
+
+
+def test_batch_level_records(gpu):
+    """gap_bfs_batch_ex: results as without records; one record per level
+    the batch ran; level 0's frontier is the set of distinct sources and each
+    level's claimed count is the next level's frontier; the records agree
+    with the lanes' oracle depths (frontier of level d = vertices some lane
+    reaches at depth d)."""
+    import torch
+    from paper_1508_03619_amd import gapbfs as gb, inputs
+    el = inputs.rmat(13, 16, seed=7301)
+    g = gb.build_csr(el.n, el.src, el.dst)
+    A = oracle.Adjacency(el.n, el.src, el.dst)
+    srcs = [int(x) for x in inputs.pick_sources(el, 40, seed=7302)]
+    srcs += srcs[:3]  # repeated sources are separate lanes
+    P = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
+    D = [torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in srcs]
+    recs = gb.bfs_batch([g], [0] * len(srcs), srcs, P, D, stats=True)
+    torch.cuda.synchronize()
+    depths = np.stack([A.bfs(s)[0] for s in srcs])
+    for i, s in enumerate(srcs):
+        assert_valid(A, s, P[i].cpu().numpy(), D[i].cpu().numpy(), depths[i], what=f"lane {i}")
+    maxd = int(depths.max())
+    assert len(recs) == maxd + 1  # levels 0..maxd expand a non-empty frontier
+    deg = np.diff(A.offsets)
+    for r in recs:
+        d = r["level"]
+        front = np.any(depths == d, axis=0)
+        assert r["frontier"] == int(front.sum()), r
+        assert r["frontier_edges"] == int(deg[front].sum()), r
+        assert r["direction"] in (1, 2)
+        if r["direction"] == 2:  # every vertex found was searched for, and read an entry
+            assert r["claimed"] <= r["unvisited"] <= r["scanned"], r
+    assert recs[0]["frontier"] == len(set(srcs))
+    for a, b in zip(recs, recs[1:]):
+        assert a["claimed"] == b["frontier"]
+    g.free()

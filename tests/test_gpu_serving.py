@@ -58,3 +58,49 @@ def test_serving_mix_equals_alone(gpu):
         assert np.array_equal(da_h, dm), f"query {q.qid}: depth alone != depth in the mix"
         assert A.check(q.source, refs[key], pa_h, da_h)[0] == 0, f"query {q.qid} alone"
     pool.free()
+
+
+def test_continuous_serving_mix_equals_alone(gpu):
+    """Continuous batching (servers that take queries into running searches):
+    every query's depths equal its depths alone and the oracle's, and both
+    parent arrays are valid; a budget of 8 outputs of the largest graph makes
+    admission wait."""
+    import torch
+    from paper_1508_03619_amd import gapbfs as gb, serving as sv
+    pool = sv.Pool(sv.pool_spec(small=True), keep_edges=True)
+    adjs = [oracle.Adjacency(el.n, el.src, el.dst) for el in pool.edges]
+    qs = sv.poisson_queries(0.0, 120, pool.sources, seed=787)
+    qs += sv.poisson_queries(3000.0, 180, pool.sources, seed=788, first_id=120)
+    results = {}
+    side = torch.cuda.Stream()
+
+    def on_done(batch, outs):
+        p, d = outs
+        with torch.cuda.stream(side):
+            results[batch[0].qid] = (p.cpu().numpy(), d.cpu().numpy())
+
+    budget = 8 * 8 * max(pool.sizes)
+    sched = sv.Scheduler(pool.sizes, budget_bytes=budget, max_lanes=64)
+    ex = sv.ContinuousExecutor(pool.graphs, slots=4, lanes=64, sources=pool.sources)
+    say(f"continuous: {len(qs)} queries, single-search graphs {sorted(ex.single_graphs)}")
+    try:
+        done = sv.serve_continuous(ex, sched, qs, on_done)
+    finally:
+        ex.close()
+    assert sorted(q.qid for q in done) == list(range(len(qs)))
+    assert ex.launch_kinds["joined"] > 0, dict(ex.launch_kinds)
+    assert sched.peak_used <= budget and sched.admission_waits > 0
+    pa = {}
+    for q in done:
+        A, g = adjs[q.graph], pool.graphs[q.graph]
+        ref = A.bfs(q.source)[0]
+        pm, dm = results[q.qid]
+        assert A.check(q.source, ref, pm, dm)[0] == 0, f"query {q.qid} in the mix"
+        if g.n not in pa:
+            pa[g.n] = (torch.empty(g.n, dtype=torch.int32, device="cuda"),
+                       torch.empty(g.n, dtype=torch.int32, device="cuda"))
+        p1, d1 = pa[g.n]
+        gb.bfs(g, q.source, p1, d1)
+        torch.cuda.synchronize()
+        assert np.array_equal(d1.cpu().numpy(), dm), f"query {q.qid}: alone != in the mix"
+    pool.free()

@@ -168,3 +168,55 @@ def test_closed_loop_keeps_client_count_in_flight():
     assert peak <= 16
     arrivals = sorted(q.arrival for q in done)
     assert arrivals[:16] == [0.0] * 16 and arrivals[16] > 0.0
+
+
+# ---- continuous batching (serve_continuous) on the simulated device ----------
+
+def sim_service(n):
+    return 2e-4 + 2e-9 * n
+
+
+@pytest.mark.parametrize("rate", [100.0, 5000.0, 0.0])
+def test_continuous_every_query_once_within_budget(rate):
+    qs = make_queries(rate, 600, seed=11)
+    sched = sv.Scheduler(SIZES, budget_bytes=40 * 8 * max(SIZES), max_lanes=16)
+    ex = sv.SimContinuous(3, 16, sim_service, SIZES)
+    done = sv.serve_continuous(ex, sched, qs)
+    assert sorted(q.qid for q in done) == list(range(600))
+    assert sched.used == 0 and sched.pending == 0
+    assert sched.peak_used <= sched.budget
+    for q in done:
+        assert q.arrival <= q.start <= q.done
+    assert ex.max_lanes_used <= 16
+
+
+def test_continuous_queries_join_running_searches():
+    """Under a backlog most queries join a server that is already running a
+    search of their graph, rather than waiting for it to finish."""
+    qs = make_queries(0.0, 400, seed=12)
+    sched = sv.Scheduler(SIZES, budget_bytes=1 << 30, max_lanes=64)
+    ex = sv.SimContinuous(2, 64, sim_service, SIZES)
+    sv.serve_continuous(ex, sched, qs)
+    assert ex.joined_running > 200
+
+
+def test_continuous_budget_binds_and_fifo_on_memory():
+    """A budget of 3 queries of the largest graph: admission stops at the
+    first query that does not fit (nothing overtakes it on memory)."""
+    qs = make_queries(0.0, 200, seed=13)
+    budget = 3 * 8 * max(SIZES)
+    sched = sv.Scheduler(SIZES, budget_bytes=budget, max_lanes=64)
+    ex = sv.SimContinuous(4, 64, sim_service, SIZES)
+    done = sv.serve_continuous(ex, sched, qs)
+    assert len(done) == 200 and sched.admission_waits > 0
+    assert sched.peak_used <= budget
+
+
+def test_continuous_closed_loop():
+    cands = [np.arange(n, dtype=np.int32) for n in SIZES]
+    qs = sv.poisson_queries(0.0, 300, cands, 14)
+    src = sv.ClosedArrivals(10, 300, lambda k: qs[k])
+    sched = sv.Scheduler(SIZES, budget_bytes=1 << 30, max_lanes=64)
+    ex = sv.SimContinuous(2, 64, sim_service, SIZES)
+    done = sv.serve_continuous(ex, sched, src)
+    assert len(done) == 300
