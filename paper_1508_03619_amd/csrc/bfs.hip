@@ -153,7 +153,7 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
     }
     StepArgs s{a.g, a.parent, a.depth, a.Q, d & 1, a.ctl, (fsel ? a.bm1 : a.bm0), a.vbm, (fsel ? a.bm0 : a.bm1),
                d, a.p.hub, a.p.chunk};
-    step_begin<BLOCK>(s, st);
+    step_begin<BLOCK>(s, st, dir == kTopDown);  // a bottom-up step reads no queue
     LaneAcc acc;
     if (dir == kTopDown)
       td_step<BLOCK, STATS, true>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);

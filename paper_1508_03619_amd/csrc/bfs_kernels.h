@@ -247,10 +247,17 @@ __device__ inline void stage_append(const StepArgs &a, Stage<BLOCK> &st, bool cl
 }
 
 // Start of a step (all threads): load the input segment prefix sums of
-// pub[d & 1] and clear the staging counters.
+// pub[d & 1] (only a step that reads the queues needs them: `segments`)
+// and clear the staging counters.
 template <int BLOCK>
-__device__ inline void step_begin(const StepArgs &a, Stage<BLOCK> &st) {
-  if (threadIdx.x < kWave) {
+__device__ inline void step_begin(const StepArgs &a, Stage<BLOCK> &st, bool segments = true) {
+  if (threadIdx.x < kWave && !segments) {
+    if (threadIdx.x == 0) {
+      st.qn = 0;
+      st.cn = 0;
+      st.hn = 0;
+    }
+  } else if (threadIdx.x < kWave) {
     // lane h < kGroups loads segment h's sizes: one round trip, not 2*kGroups
     const int lane = threadIdx.x;
     const Published &P = a.ctl->pub[a.d & 1];
@@ -829,33 +836,89 @@ __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *pare
                                           uint64_t *vbm, int64_t gwave, int64_t nwaves) {
   const int lane = lane_id();
   const int64_t nwords = (g.n + kWave - 1) / kWave;
-  for (int64_t w = gwave; w < nwords; w += nwaves) {
-    const int64_t v = w * kWave + lane;
-    bool visited = true, front = false;
-    if (v < g.n) {
-      const int32_t p = parent[v];
-      if (g.directed)
-        visited = (p >= 0) || (g.row_ptr_in[v + 1] == g.row_ptr_in[v]);
-      else
-        visited = (p >= 0) || (p == kIsolated);
-      front = depth[v] == d;
+  // kConvU words per pass: all their loads are issued before the first
+  // ballot waits, so a wave keeps 2 * kConvU loads in flight
+  constexpr int kConvU = 4;
+  for (int64_t w0 = gwave; w0 < nwords; w0 += kConvU * nwaves) {
+    int32_t p[kConvU], dv[kConvU];
+#pragma unroll
+    for (int u = 0; u < kConvU; ++u) {
+      const int64_t v = (w0 + u * nwaves) * kWave + lane;
+      const bool in = w0 + u * nwaves < nwords && v < g.n;
+      p[u] = in ? parent[v] : 0;
+      dv[u] = in ? depth[v] : -1;
     }
-    const uint64_t bv = __ballot(visited);
-    const uint64_t bf = __ballot(front);
-    if (lane == 0) {
-      vbm[w] = bv;
-      fbm[w] = bf;
+#pragma unroll
+    for (int u = 0; u < kConvU; ++u) {
+      const int64_t w = w0 + u * nwaves;
+      if (w >= nwords) break;  // wave-uniform
+      const int64_t v = w * kWave + lane;
+      bool visited = true;
+      if (v < g.n) {
+        if (g.directed)
+          visited = (p[u] >= 0) || (g.row_ptr_in[v + 1] == g.row_ptr_in[v]);
+        else
+          visited = (p[u] >= 0) || (p[u] == kIsolated);
+      }
+      const uint64_t bv = __ballot(visited);
+      const uint64_t bf = __ballot(v < g.n && dv[u] == d);
+      if (lane == 0) {
+        vbm[w] = bv;
+        fbm[w] = bf;
+      }
     }
   }
 }
 
 // Per-search initialisation (timed, Section 2.3): parent <- -degree
 // (Section 3, BFS), depth <- -1, then the source.
+// Groups of four vertices go with 16-byte stores when both outputs are
+// 16-byte aligned, kInitU groups per thread per pass with every row-offset
+// load issued before the first store (the compiler cannot move a load of
+// row_ptr above a store to parent or depth by itself); the rest one by one.
+__device__ inline int32_t initial_parent(int64_t deg) {
+  return deg ? (int32_t)(-deg) : kIsolated;
+}
+
 __device__ inline void init_vertices(const DevGraph &g, int32_t *parent, int32_t *depth,
                                      int32_t source, int64_t tid, int64_t nthreads) {
-  for (int64_t v = tid; v < g.n; v += nthreads) {
-    const int64_t deg = g.row_ptr[v + 1] - g.row_ptr[v];
-    int32_t p = deg ? (int32_t)(-deg) : kIsolated;
+  constexpr int kInitU = 4;
+  const bool vec = ((reinterpret_cast<uintptr_t>(parent) | reinterpret_cast<uintptr_t>(depth) |
+                     reinterpret_cast<uintptr_t>(g.row_ptr)) & 15u) == 0;
+  const int64_t n4 = vec ? g.n / 4 : 0;
+  for (int64_t q0 = tid; q0 < n4; q0 += kInitU * nthreads) {
+    int64_t r[kInitU][5];
+#pragma unroll
+    for (int u = 0; u < kInitU; ++u) {
+      const int64_t q = q0 + u * nthreads;
+      if (q < n4) {
+        const longlong2 a = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q);
+        const longlong2 b = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q + 2);
+        r[u][0] = a.x;
+        r[u][1] = a.y;
+        r[u][2] = b.x;
+        r[u][3] = b.y;
+        r[u][4] = g.row_ptr[4 * q + 4];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kInitU; ++u) {
+      const int64_t q = q0 + u * nthreads;
+      if (q >= n4) break;
+      int4 p = make_int4(initial_parent(r[u][1] - r[u][0]), initial_parent(r[u][2] - r[u][1]),
+                         initial_parent(r[u][3] - r[u][2]), initial_parent(r[u][4] - r[u][3]));
+      int4 dd = make_int4(-1, -1, -1, -1);
+      const int64_t k = (int64_t)source - 4 * q;
+      if (k == 0) { p.x = source; dd.x = 0; }
+      if (k == 1) { p.y = source; dd.y = 0; }
+      if (k == 2) { p.z = source; dd.z = 0; }
+      if (k == 3) { p.w = source; dd.w = 0; }
+      reinterpret_cast<int4 *>(parent)[q] = p;
+      reinterpret_cast<int4 *>(depth)[q] = dd;
+    }
+  }
+  for (int64_t v = 4 * n4 + tid; v < g.n; v += nthreads) {
+    int32_t p = initial_parent(g.row_ptr[v + 1] - g.row_ptr[v]);
     int32_t dd = -1;
     if (v == source) {
       p = source;
@@ -886,8 +949,29 @@ __device__ inline Totals init_source(const DevGraph &g, const Queues &Q, Ctl *ct
 }
 
 // Final pass (Section 3, BFS): every negative parent becomes -1.
+// Groups of four with 16-byte accesses when `parent` is 16-byte aligned,
+// kFixU loads in flight per thread before the first store.
 __device__ inline void fixup_parents(int64_t n, int32_t *parent, int64_t tid, int64_t nthreads) {
-  for (int64_t v = tid; v < n; v += nthreads) {
+  constexpr int kFixU = 4;
+  const int64_t n4 = (reinterpret_cast<uintptr_t>(parent) & 15u) == 0 ? n / 4 : 0;
+  int4 *p4 = reinterpret_cast<int4 *>(parent);
+  for (int64_t q0 = tid; q0 < n4; q0 += kFixU * nthreads) {
+    int4 x[kFixU];
+#pragma unroll
+    for (int u = 0; u < kFixU; ++u) {
+      const int64_t q = q0 + u * nthreads;
+      if (q < n4) x[u] = p4[q];
+    }
+#pragma unroll
+    for (int u = 0; u < kFixU; ++u) {
+      const int64_t q = q0 + u * nthreads;
+      if (q >= n4) break;
+      if (x[u].x < -1 || x[u].y < -1 || x[u].z < -1 || x[u].w < -1)
+        p4[q] = make_int4(x[u].x < -1 ? -1 : x[u].x, x[u].y < -1 ? -1 : x[u].y,
+                          x[u].z < -1 ? -1 : x[u].z, x[u].w < -1 ? -1 : x[u].w);
+    }
+  }
+  for (int64_t v = 4 * n4 + tid; v < n; v += nthreads) {
     const int32_t p = parent[v];
     if (p < -1) parent[v] = -1;
   }

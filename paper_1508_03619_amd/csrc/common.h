@@ -282,7 +282,9 @@ struct NoDecision {
 // generation word advances by 2 and carries the decision's flag in bit 0;
 // `flag` returns it to every participant.
 // Bounded: a workgroup that waits longer than B.limit records GAP_ETIMEOUT
-// in ctl->err.  Returns false once an error has been recorded.
+// in ctl->err.  Returns false when this wait saw an error recorded (before
+// the release, or by this workgroup's own time-out); an error recorded
+// after the release is seen at the next wait.
 template <class Decide>
 __device__ inline bool grid_sync_x(Ctl *ctl, BarrierSet B, unsigned int nblocks, const Totals &part,
                                    int publish, int bs, const Decide &decide, int &flag) {
@@ -325,9 +327,19 @@ __device__ inline bool grid_sync_x(Ctl *ctl, BarrierSet B, unsigned int nblocks,
       }
     }
     if (!released) {
+      // the error word is read in the same round trip as the flag: an
+      // error recorded before the release stops this workgroup here, one
+      // recorded later at its next wait (no load after the release)
       const uint64_t t0 = rt_clock();
       unsigned int v;
-      while ((v = ld_agent(&B.gen[g].gen)) == gen0) {
+      for (;;) {
+        v = ld_agent(&B.gen[g].gen);
+        const int e = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v != gen0) break;
+        if (e != 0) {
+          ok = 0;
+          break;
+        }
         __builtin_amdgcn_s_sleep(1);
         if (rt_clock() - t0 > B.limit) {
           __hip_atomic_store(&ctl->err, (int)GAP_ETIMEOUT, __ATOMIC_RELAXED,
@@ -339,7 +351,6 @@ __device__ inline bool grid_sync_x(Ctl *ctl, BarrierSet B, unsigned int nblocks,
       fl = (int)(v & 1u);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     s_ok = ok;
     s_flag = fl;
   }
