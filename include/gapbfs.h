@@ -417,7 +417,10 @@ typedef struct gap_params {
                             rest wait (0 = every level on the whole grid) */
   int32_t lds_bitmap;    /* persistent single-source schedule: 1 = bottom-up
                             steps copy the frontier bitmap (n/8 bytes) into
-                            each workgroup's LDS when it fits, 0 = never */
+                            each workgroup's LDS, the whole of it when it
+                            fits, else its low words up to the LDS left
+                            beside the kernel's own (probes of higher
+                            vertex ids read the global copy); 0 = never */
   int32_t wait_limit_us; /* bound of one device-side wait without progress
                             (a grid barrier, or a parked workgroup waiting
                             for the small group), in microseconds; 0 = the

@@ -29,7 +29,7 @@ struct SearchArgs {
   Params p;
   DevLevelRec *recs;
   int32_t max_recs;
-  int32_t lds_bm;  // 1: the frontier bitmap fits the dynamic LDS of each workgroup
+  int64_t lds_words;  // frontier bitmap words held in each workgroup's dynamic LDS (0: none)
 };
 
 // ---- persistent cooperative kernel -------------------------------------------
@@ -81,7 +81,7 @@ struct SmallDecision {
 template <int BLOCK, bool STATS>
 __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
   __shared__ Stage<BLOCK> st;
-  extern __shared__ uint64_t lds_fbm[];  // frontier bitmap copy (lds_bm)
+  extern __shared__ uint64_t lds_fbm[];  // frontier bitmap words [0, lds_words)
   const int64_t nthreads = (int64_t)gridDim.x * BLOCK;
   const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int64_t nwaves = nthreads / kWave;
@@ -154,6 +154,9 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
     StepArgs s{a.g, a.parent, a.depth, a.Q, d & 1, a.ctl, (fsel ? a.bm1 : a.bm0), a.vbm, (fsel ? a.bm0 : a.bm1),
                d, a.p.hub, a.p.chunk};
     step_begin<BLOCK>(s, st, dir == kTopDown);  // a bottom-up step reads no queue
+    // the LDS copy of the frontier bitmap pays when a workgroup has more
+    // list entries left to probe (mu bounds them) than words to copy
+    const int64_t lw = (mu / (int64_t)nblocks >= a.lds_words) ? a.lds_words : 0;
     LaneAcc acc;
     if (dir == kTopDown)
       td_step<BLOCK, STATS, true>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
@@ -162,11 +165,11 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
       const int64_t per = (nwords_all + nblocks - 1) / nblocks;
       const int64_t wlo = (int64_t)blockIdx.x * per < nwords_all ? (int64_t)blockIdx.x * per : nwords_all;
       const int64_t whi = wlo + per < nwords_all ? wlo + per : nwords_all;
-      bu_step_refill<BLOCK, STATS, GAP_BU_SLOTS>(s, st, acc, wlo, whi, a.lds_bm ? lds_fbm : nullptr);
+      bu_step_refill<BLOCK, STATS, GAP_BU_SLOTS>(s, st, acc, wlo, whi, lds_fbm, lw);
     } else
       bu_step<BLOCK, STATS, GAP_BU_WORDS, GAP_BU_ROUND2, false>(s, st, acc, gwave,
                                                                 nwaves,  // never on the small group
-                                                                a.lds_bm ? lds_fbm : nullptr);
+                                                                lds_fbm, lw);
     const Totals t = step_end<BLOCK>(s, st, acc);
     const int fsel_next = (dir == kBottomUp) ? (fsel ^ 1) : fsel;
     const SmallDecision dec{a.g.n, mu, nv, (int64_t)a.p.small, dir, d, have_bm ? 1 : 0, fsel_next,
@@ -340,16 +343,27 @@ static gap_status launch_persistent(const SearchArgs &a, const DeviceInfo *di, i
                                     int split, int lds_bitmap, hipStream_t stream) {
   auto kern = k_bfs_persistent<BLOCK, STATS>;
   SearchArgs args = a;
-  // the frontier bitmap goes to LDS when it fits next to the static staging
+  // the frontier bitmap goes to LDS next to the static staging: all of it
+  // when it fits, else as many of its low words as the LDS left to each of
+  // the workgroups that share a compute unit holds (at least kMinLdsWords)
+  constexpr int64_t kMinLdsWords = 1024;
   size_t shmem = 0;
-  args.lds_bm = 0;
+  args.lds_words = 0;
   if (lds_bitmap) {
     hipFuncAttributes attr{};
-    const size_t bytes = sizeof(uint64_t) * (size_t)((a.g.n + kWave - 1) / kWave);
+    int fit0 = 0;
     if (hipFuncGetAttributes(&attr, (const void *)kern) == hipSuccess &&
-        attr.sharedSizeBytes + bytes + 1024 <= (size_t)di->lds_per_block) {
-      shmem = bytes;
-      args.lds_bm = 1;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit0, kern, BLOCK, 0) == hipSuccess &&
+        fit0 > 0) {
+      const int want = blocks_per_cu > 0 && blocks_per_cu < fit0 ? blocks_per_cu : fit0;
+      const int64_t room = std::min<int64_t>(di->lds_per_block, di->lds_per_cu / want) -
+                           (int64_t)attr.sharedSizeBytes - 1024;
+      const int64_t nwords = (a.g.n + kWave - 1) / kWave;
+      const int64_t words = std::min<int64_t>(nwords, room / (int64_t)sizeof(uint64_t));
+      if (words >= std::min<int64_t>(nwords, kMinLdsWords) && words > 0) {
+        shmem = (size_t)words * sizeof(uint64_t);
+        args.lds_words = words;
+      }
     }
     (void)hipGetLastError();
   }

@@ -462,10 +462,39 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
 #define GAP_BU_ROUND2 4
 #endif
 
+// The frontier bitmap F_d as a bottom-up step probes it: words [0, lw) from
+// the workgroup's LDS copy, the rest from global memory (the L2-held copy).
+// Adjacency lists are sorted, so the first entries of a list (those a
+// bottom-up search reads first, and most often stops at) are the smallest
+// vertex ids: an LDS copy of the low words of the bitmap takes most of the
+// probes even when the whole bitmap does not fit.
+struct FrontierBits {
+  const uint64_t *lds;
+  int64_t lw;
+  const uint64_t *g;
+  __device__ __forceinline__ bool test(int32_t u) const {
+    const int64_t w = u >> 6;
+    const uint64_t word = w < lw ? lds[w] : g[w];
+    return (word >> (u & 63)) & 1ull;
+  }
+};
+
+// Copies the first lw words of F_d into LDS (whole workgroup, then a
+// workgroup barrier); lw = 0 keeps every probe on the global copy.
+template <int BLOCK>
+__device__ inline FrontierBits frontier_bits(const StepArgs &a, uint64_t *lfbm, int64_t lw) {
+  const int64_t nwords = (a.g.n + kWave - 1) / kWave;
+  if (!lfbm) lw = 0;
+  if (lw > nwords) lw = nwords;
+  for (int64_t i = threadIdx.x; i < lw; i += BLOCK) lfbm[i] = a.fbm[i];
+  if (lw) __syncthreads();
+  return FrontierBits{lfbm, lw, a.fbm};
+}
+
 // One round over the J vertices of a lane: RR entries each from e[j] on.
 // Returns whether any of them is still searching.
 template <int J, int RR, bool STATS>
-__device__ inline bool bu_round(const int32_t *__restrict__ col, const uint64_t *fb, bool (&act)[J],
+__device__ inline bool bu_round(const int32_t *__restrict__ col, const FrontierBits &fb, bool (&act)[J],
                                 int64_t (&e)[J], int32_t (&rem)[J], int32_t (&pu)[J], LaneAcc &acc) {
   static_assert(RR % 4 == 0, "runs are read 16 bytes at a time");
   int32_t u[J][RR];
@@ -483,7 +512,7 @@ __device__ inline bool bu_round(const int32_t *__restrict__ col, const uint64_t 
   for (int j = 0; j < J; ++j)
 #pragma unroll
     for (int k = 0; k < RR; ++k)
-      hit[j][k] = u[j][k] >= 0 && ((fb[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
+      hit[j][k] = u[j][k] >= 0 && fb.test(u[j][k]);
   bool more = false;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -509,21 +538,18 @@ __device__ inline bool bu_round(const int32_t *__restrict__ col, const uint64_t 
   return more;
 }
 
-// lfbm: when not NULL, LDS room for the whole frontier bitmap; the step
-// first copies F_d there and probes LDS instead of the L2-held copy.
+// lfbm: when not NULL, LDS room for the first lw words of the frontier
+// bitmap; the step first copies them there and probes LDS for them
+// instead of the L2-held copy.
 // QUEUE: also append F_{d+1} to the vertex queue (and hub chunk items); a
 // caller that passes false only counts the totals, and turns the bitmap
 // into a queue itself when a top-down step follows (queue_from_bitmap).
 template <int BLOCK, bool STATS, int J = GAP_BU_WORDS, int R2 = GAP_BU_ROUND2, bool QUEUE = true>
 __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
-                        int64_t nwaves, uint64_t *lfbm = nullptr) {
+                        int64_t nwaves, uint64_t *lfbm = nullptr, int64_t lw = 0) {
   const int lane = lane_id();
   const int64_t nwords = (a.g.n + kWave - 1) / kWave;
-  if (lfbm) {
-    for (int64_t i = threadIdx.x; i < nwords; i += BLOCK) lfbm[i] = a.fbm[i];
-    __syncthreads();
-  }
-  const uint64_t *fb = lfbm ? lfbm : a.fbm;
+  const FrontierBits fb = frontier_bits<BLOCK>(a, lfbm, lw);
   for (int64_t base = gwave * J; base < nwords; base += nwaves * J) {
     uint64_t vis[J];
     int64_t e[J];       // next adjacency entry
@@ -620,19 +646,15 @@ __host__ __device__ constexpr int64_t bu_refill_words() {
 
 template <int BLOCK, bool STATS, int J>
 __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t wlo,
-                               int64_t whi, uint64_t *lfbm) {
+                               int64_t whi, uint64_t *lfbm, int64_t lw) {
   uint64_t *found = reinterpret_cast<uint64_t *>(st.q);
   unsigned int *cursor = &st.hbase;
   const int lane = lane_id();
   const int64_t nw = whi > wlo ? whi - wlo : 0;
-  if (lfbm) {
-    const int64_t nwords = (a.g.n + kWave - 1) / kWave;
-    for (int64_t i = threadIdx.x; i < nwords; i += BLOCK) lfbm[i] = a.fbm[i];
-  }
   for (int64_t i = threadIdx.x; i < nw; i += BLOCK) found[i] = 0ull;
   if (threadIdx.x == 0) *cursor = 0u;
+  const FrontierBits fb = frontier_bits<BLOCK>(a, lfbm, lw);
   __syncthreads();
-  const uint64_t *fb = lfbm ? lfbm : a.fbm;
   const int32_t *__restrict__ col = a.g.col_in;
   const int64_t *__restrict__ rp = a.g.row_ptr_in;
 
@@ -738,7 +760,7 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
     for (int j = 0; j < J; ++j)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        hit[j][k] = u[j][k] >= 0 && ((fb[u[j][k] >> 6] >> (u[j][k] & 63)) & 1ull);
+        hit[j][k] = u[j][k] >= 0 && fb.test(u[j][k]);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       if (v[j] < 0) continue;

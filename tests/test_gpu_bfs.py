@@ -243,8 +243,10 @@ def test_small_group_levels(gpu, block):
 
 
 def test_lds_frontier_bitmap(gpu):
-    """Bottom-up steps with the frontier bitmap in LDS (graphs small enough)
-    and in L2 (a graph too large for LDS, or the option off), with refilled
+    """Bottom-up steps with the frontier bitmap wholly in LDS (R-MAT 16),
+    its low words in LDS and the rest in L2 (a 10^6-vertex grid and a
+    2^21-vertex graph: probes on both sides of the split), and in L2 only
+    (the option off), with refilled
     lanes over per-workgroup ranges (ranges of 4, 128 and 61 words: shorter
     than a chunk, several chunks, a ragged last chunk) and with fixed words
     per wave."""
