@@ -444,6 +444,14 @@ typedef struct gap_params {
                             this long after it starts, then finishes the
                             searches it holds and exits (0 = it takes
                             requests at its first boundary only) */
+  int32_t td_plain;      /* persistent single-source schedule: a top-down
+                            level whose frontier edges exceed n / td_plain
+                            claims vertices with plain stores of parent and
+                            depth instead of compare-and-swap (any frontier
+                            neighbour is a valid parent), and F_{d+1} and its
+                            totals are then read back from the depths by one
+                            pass over the vertices; 0 = every level claims by
+                            compare-and-swap.  Default 8. */
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

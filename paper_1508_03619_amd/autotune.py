@@ -45,10 +45,11 @@ SPACE: Dict[str, List[int]] = {
     "lds_bitmap": [0, 1],
     "blocks_per_cu": [1, 2],
     "bu_mapping": [0, 1],
+    "td_plain": [0, 2, 4, 8, 16, 32],
     "batch_words": [1, 2, 4],
 }
 ORDER = ["block", "blocks_per_cu", "alpha", "beta", "hub_degree", "chunk_edges", "small_frontier",
-         "lds_bitmap", "bu_mapping", "batch_alpha", "batch_beta", "batch_words", "mode",
+         "lds_bitmap", "bu_mapping", "td_plain", "batch_alpha", "batch_beta", "batch_words", "mode",
          "graph_chunk"]
 
 # Tuning set: the benchmark's graph shapes at reduced size, other seeds.

@@ -200,6 +200,7 @@ static gap_params default_params() {
   p.bu_mapping = 0;
   p.batch_words = 4;
   p.serve_window_us = 5000;
+  p.td_plain = 8;
   return p;
 }
 
@@ -261,6 +262,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.serve_window_us < 0) {
     set_error("params: serve_window_us must be >= 0");
+    return GAP_EINVAL;
+  }
+  if (p.td_plain < 0) {
+    set_error("params: td_plain must be >= 0");
     return GAP_EINVAL;
   }
   if (p.bu_mapping != 0 && p.bu_mapping != 1) {

@@ -104,7 +104,8 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
   bool have_bm = false;
   int64_t mu = a.g.nnz, nf_prev = 0;
   int fsel = 0;
-  bool small = false;  // this level runs on the small group
+  bool small = false;     // this level runs on the small group
+  bool bm_ready = false;  // F_d's bitmaps were read back at the end of a plain-claim level
   for (;;) {
     const Published &P = a.ctl->pub[d & 1];
     const int64_t nv = uni((int64_t)ld_agent(&P.t.nv));
@@ -123,14 +124,15 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
     const unsigned long long level_t0 = STATS ? rt_clock() : 0ull;
     mu -= mf;
     const int32_t ndir = decide_direction(dir, nv, mf, mu, nf_prev, a.g.n, a.p, d);
-    if (ndir == kBottomUp && !(dir == kBottomUp && have_bm)) {
+    if (ndir == kBottomUp && !bm_ready && !(dir == kBottomUp && have_bm)) {
       convert_to_bitmaps(a.g, a.parent, a.depth, d, (fsel ? a.bm1 : a.bm0), a.vbm, gwave, nwaves);
       if (!grid_sync(a.ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
-      have_bm = true;
     }
-    if (dir == kBottomUp && ndir == kTopDown) {
-      // the bottom-up steps left F_d as a bitmap only: queue it for this
-      // top-down step (buffer set d & 1), on the workgroups that run it
+    if (ndir == kBottomUp) have_bm = true;
+    if ((dir == kBottomUp || bm_ready) && ndir == kTopDown) {
+      // the bottom-up steps (or the read-back after plain claims) left F_d
+      // as a bitmap only: queue it for this top-down step (buffer set
+      // d & 1), on the workgroups that run it
       StepArgs c{a.g, a.parent, a.depth, a.Q, (d & 1) ^ 1, a.ctl, nullptr, nullptr, nullptr,
                  d, a.p.hub, a.p.chunk};
       queue_from_bitmap<BLOCK>(c, st, (fsel ? a.bm1 : a.bm0), gwave,
@@ -141,7 +143,13 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
         return;
     }
     if (ndir == kTopDown) have_bm = false;
+    bm_ready = false;
     dir = ndir;
+    // a large top-down level claims by plain stores (never on the small
+    // group, whose parked workgroups would not know that F_{d+1} comes back
+    // as bitmaps)
+    const bool plain = dir == kTopDown && !small && a.p.td_plain > 0 &&
+                       mf > a.g.n / (int64_t)a.p.td_plain;
     if (STATS && tid == 0 && d < a.max_recs) {
       DevLevelRec r = {};
       r.level = d;
@@ -158,7 +166,9 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
     // list entries left to probe (mu bounds them) than words to copy
     const int64_t lw = (mu / (int64_t)nblocks >= a.lds_words) ? a.lds_words : 0;
     LaneAcc acc;
-    if (dir == kTopDown)
+    if (dir == kTopDown && plain)
+      td_step<BLOCK, STATS, true, true>(s, st, acc, gwave, nwaves);
+    else if (dir == kTopDown)
       td_step<BLOCK, STATS, true>(s, st, acc, gwave, small ? (int64_t)nsmall * (BLOCK / kWave) : nwaves);
     else if (a.p.bu_mapping == 0 && (nwords_all + nblocks - 1) / nblocks <= bu_refill_words<BLOCK>()) {
       // never on the small group: every workgroup takes its share of the words
@@ -170,7 +180,19 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
       bu_step<BLOCK, STATS, GAP_BU_WORDS, GAP_BU_ROUND2, false>(s, st, acc, gwave,
                                                                 nwaves,  // never on the small group
                                                                 lds_fbm, lw);
-    const Totals t = step_end<BLOCK>(s, st, acc);
+    Totals t = step_end<BLOCK>(s, st, acc);
+    if (plain) {
+      // F_{d+1} is every vertex at depth d + 1: after the claims' barrier,
+      // build its bitmaps (in the current slot: a top-down step keeps fsel)
+      // and count it, for the barrier below and the next level
+      const unsigned long long scanned = t.scanned;  // thread 0's
+      if (!grid_sync(a.ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
+      step_begin<BLOCK>(s, st, false);
+      convert_to_bitmaps(a.g, a.parent, a.depth, d + 1, (fsel ? a.bm1 : a.bm0), a.vbm, gwave, nwaves,
+                         &acc);
+      t = step_end<BLOCK>(s, st, acc);
+      t.scanned += scanned;
+    }
     const int fsel_next = (dir == kBottomUp) ? (fsel ^ 1) : fsel;
     const SmallDecision dec{a.g.n, mu, nv, (int64_t)a.p.small, dir, d, have_bm ? 1 : 0, fsel_next,
                             a.p, small, small_enabled};
@@ -182,6 +204,7 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
     small_next = uni(small_next);
     fsel = fsel_next;
     nf_prev = nv;
+    bm_ready = plain;
     ++d;
     if (small_next && !small && blockIdx.x >= nsmall) {
       // park until the small group hands the search back
@@ -193,6 +216,7 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
       fsel = uni(ps.fsel);
       mu = uni((int64_t)ps.mu);
       nf_prev = uni((int64_t)ps.nf_prev);
+      bm_ready = false;  // the small group (which never claims by plain stores) hands over
       continue;
     }
     small = small_next != 0;
@@ -548,7 +572,7 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
   a.vbm = ws->bm[2];
   a.ctl = ws->ctl;
   a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier,
-               p.bu_mapping, 0, 0};
+               p.bu_mapping, p.td_plain, 0, 0};
   set_wait_limits(a.p, p.wait_limit_us);
   a.sticky = ws->sticky;
   a.recs = want_stats ? ws->recs : nullptr;
@@ -729,7 +753,7 @@ gap_status run_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent, 
   a.ctl_clear = nullptr;
   a.sticky = reinterpret_cast<int *>(base);
   a.p = Params{p.alpha, p.beta, p.direction, p.hub_degree, p.chunk_edges, p.small_frontier,
-               p.bu_mapping, 0, 0};
+               p.bu_mapping, p.td_plain, 0, 0};
   set_wait_limits(a.p, p.wait_limit_us);
   a.recs = nullptr;
   a.max_recs = 0;

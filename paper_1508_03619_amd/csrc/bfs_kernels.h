@@ -357,6 +357,28 @@ __device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &a
   }
 }
 
+// Plain-store claims of four edge batches: every v[k] that a probe finds
+// unvisited gets parent u[k] and depth d + 1 by ordinary stores.  Several
+// frontier vertices may write one v; whichever store lands is a frontier
+// neighbour, so the parent is valid and the depth the same.  Nothing is
+// appended: F_{d+1} is read back from the depths after the level's barrier
+// (convert_to_bitmaps with totals), which also counts it exactly once.
+template <bool STATS>
+__device__ inline void td_plain4(const StepArgs &a, LaneAcc &acc, const int32_t (&v)[4],
+                                 const int32_t (&u)[4]) {
+  int32_t p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = v[k] >= 0 ? a.parent[v[k]] : 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (v[k] >= 0 && p[k] < 0) {
+      a.parent[v[k]] = u[k];
+      a.depth[v[k]] = a.d + 1;
+    }
+    if (STATS && v[k] >= 0) acc.scanned += 1;
+  }
+}
+
 // Top-down step: every edge (u, v) with u in F_d is tried once.
 //  * hub chunk items: one wave walks `chunk` consecutive edges of one hub,
 //    256 edges per round;
@@ -367,8 +389,8 @@ __device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &a
 // SPREAD: hand the items round the workgroups first (the persistent
 // kernel); the per-level kernels keep consecutive items on a workgroup's
 // waves, which measured faster there (17.6 against 20.7 us per level on a
-// 4096^2 grid).
-template <int BLOCK, bool STATS, bool SPREAD = false>
+// 4096^2 grid).  PLAIN: claims by plain stores (td_plain4), no appends.
+template <int BLOCK, bool STATS, bool SPREAD = false, bool PLAIN = false>
 __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
                         int64_t nwaves) {
   const int lane = lane_id();
@@ -396,7 +418,10 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
         v[k] = e < end ? a.g.col[e] : -1;
         u[k] = uu;
       }
-      td_claim4<BLOCK, STATS>(a, st, acc, v, u);
+      if constexpr (PLAIN)
+        td_plain4<STATS>(a, acc, v, u);
+      else
+        td_claim4<BLOCK, STATS>(a, st, acc, v, u);
     }
   }
   // Vertices per wave: up to 64, fewer when the frontier is small so that
@@ -439,7 +464,10 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] = ea[k] >= 0 ? a.g.col[ea[k]] : -1;
-      td_claim4<BLOCK, STATS>(a, st, acc, v, u);
+      if constexpr (PLAIN)
+        td_plain4<STATS>(a, acc, v, u);
+      else
+        td_claim4<BLOCK, STATS>(a, st, acc, v, u);
     }
   }
 }
@@ -638,6 +666,11 @@ constexpr int kBuChunk = 16;
 #ifndef GAP_BU_SLOTS
 #define GAP_BU_SLOTS 3
 #endif
+// List entries a round reads for a vertex past its head record (a multiple
+// of 4: 16-byte loads).
+#ifndef GAP_BU_RUN
+#define GAP_BU_RUN 4
+#endif
 
 template <int BLOCK>
 __host__ __device__ constexpr int64_t bu_refill_words() {
@@ -743,34 +776,43 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
 #pragma unroll
     for (int j = 0; j < J; ++j) held |= v[j] >= 0;
     if (__ballot(held) == 0ull) break;
-    // ---- one round: four entries of every held vertex ----
-    int32_t u[J][4];
+    // ---- one round: the head record (four entries) of a fresh vertex,
+    // RUN entries of the column array for one that missed before ----
+    constexpr int RUN = GAP_BU_RUN;
+    int32_t u[J][RUN];
+    int32_t adv[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      i32x4_a4 w = {-1, -1, -1, -1};
-      if (v[j] >= 0)
-        w = *reinterpret_cast<const i32x4_a4 *>(fresh[j] ? reinterpret_cast<const int32_t *>(a.g.head_in + v[j])
-                                                         : col + e[j]);
-      fresh[j] = false;
+      const bool head = fresh[j];
+      adv[j] = head ? 4 : RUN;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) u[j][k] = (v[j] >= 0 && k < rem[j]) ? w[k] : -1;
+      for (int q = 0; q < RUN / 4; ++q) {
+        i32x4_a4 w = {-1, -1, -1, -1};
+        if (v[j] >= 0 && 4 * q < rem[j] && (q == 0 || !head))
+          w = *reinterpret_cast<const i32x4_a4 *>(
+              head ? reinterpret_cast<const int32_t *>(a.g.head_in + v[j]) : col + e[j] + 4 * q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          u[j][4 * q + k] = (v[j] >= 0 && 4 * q + k < rem[j] && 4 * q + k < adv[j]) ? w[k] : -1;
+      }
+      fresh[j] = false;
     }
-    bool hit[J][4];
+    bool hit[J][RUN];
 #pragma unroll
     for (int j = 0; j < J; ++j)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < RUN; ++k)
         hit[j][k] = u[j][k] >= 0 && fb.test(u[j][k]);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       if (v[j] < 0) continue;
       int32_t pu = -1;
 #pragma unroll
-      for (int k = 3; k >= 0; --k)
+      for (int k = RUN - 1; k >= 0; --k)
         if (hit[j][k]) pu = u[j][k];
       if (STATS) {
         int used = 0;
-        for (int k = 0; k < 4 && k < rem[j]; ++k) {
+        for (int k = 0; k < adv[j] && k < rem[j]; ++k) {
           ++used;
           if (hit[j][k]) break;
         }
@@ -788,8 +830,8 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
         acc.nv += 1;
         v[j] = -1;
       } else {
-        e[j] += 4;
-        rem[j] -= 4;
+        e[j] += adv[j];
+        rem[j] -= adv[j];
         if (rem[j] <= 0) v[j] = -1;
       }
     }
@@ -852,10 +894,13 @@ __device__ void queue_from_bitmap(const StepArgs &a, Stage<BLOCK> &st, const uin
 // visited bitmap (parent >= 0; vertices that no edge enters and padding
 // count as visited so whole words can be skipped).  Undirected, "no edge
 // enters" is degree 0, which the parent encoding already holds; directed,
-// it is in-degree 0, read from the in-lists.
+// it is in-degree 0, read from the in-lists.  acc: also count F_d into it
+// (vertices, and their out-degrees read from the row offsets) -- after a
+// level of plain-store claims, the frontier's only exact count.
 __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *parent,
                                           const int32_t *depth, int32_t d, uint64_t *fbm,
-                                          uint64_t *vbm, int64_t gwave, int64_t nwaves) {
+                                          uint64_t *vbm, int64_t gwave, int64_t nwaves,
+                                          LaneAcc *acc = nullptr) {
   const int lane = lane_id();
   const int64_t nwords = (g.n + kWave - 1) / kWave;
   // kConvU words per pass: all their loads are issued before the first
@@ -882,11 +927,16 @@ __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *pare
         else
           visited = (p[u] >= 0) || (p[u] == kIsolated);
       }
+      const bool front = v < g.n && dv[u] == d;
       const uint64_t bv = __ballot(visited);
-      const uint64_t bf = __ballot(v < g.n && dv[u] == d);
+      const uint64_t bf = __ballot(front);
       if (lane == 0) {
         vbm[w] = bv;
         fbm[w] = bf;
+      }
+      if (acc && front) {
+        acc->nv += 1;
+        acc->mf += (unsigned long long)(g.row_ptr[v + 1] - g.row_ptr[v]);
       }
     }
   }

@@ -104,6 +104,7 @@ struct Params {
   int32_t alpha, beta, direction, hub, chunk;
   int32_t small;  // top-down levels with |F| and m_f at most this run on the small group
   int32_t bu_mapping;  // persistent bottom-up steps: 0 refilled lanes, 1 fixed words per wave
+  int32_t td_plain;    // persistent top-down levels with m_f > n / td_plain claim by plain stores (0: never)
   uint64_t wait;       // bound of one barrier wait (real-time ticks)
   uint64_t wait_park;  // bound of a parked workgroup's wait without progress
 };

@@ -789,7 +789,7 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
   a.ctl = reinterpret_cast<MsCtl *>(base + o_ctl);
   // bottom-up cannot stop early while any lane still misses a vertex, so the
   // batch has its own switching thresholds
-  a.p = Params{p.batch_alpha, p.batch_beta, p.direction, p.hub_degree, p.chunk_edges, 0, 0, 0, 0};
+  a.p = Params{p.batch_alpha, p.batch_beta, p.direction, p.hub_degree, p.chunk_edges, 0, 0, 0, 0, 0};
   set_wait_limits(a.p, p.wait_limit_us);
   a.sticky = ws->sticky;
   const int64_t *d_tile_base = reinterpret_cast<const int64_t *>(base + o_tb);

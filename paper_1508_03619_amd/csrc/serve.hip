@@ -604,7 +604,7 @@ gap_status server_launch(gap_server *s) {
     return GAP_ENOMEM;
   }
   a.sticky = ws->sticky;
-  a.p = Params{p.batch_alpha, p.batch_beta, p.direction, p.hub_degree, p.chunk_edges, 0, 0, 0, 0};
+  a.p = Params{p.batch_alpha, p.batch_beta, p.direction, p.hub_degree, p.chunk_edges, 0, 0, 0, 0, 0};
   set_wait_limits(a.p, p.wait_limit_us);
   a.gen = s->gen;
   a.window = (unsigned long long)(p.serve_window_us > 0 ? p.serve_window_us : 1) * kTicksPerUs;

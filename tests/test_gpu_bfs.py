@@ -14,7 +14,9 @@ pytestmark = pytest.mark.gpu
 SCHEDULES = [dict(mode=m, direction=d) for m in (0, 1, 2) for d in (0, 1, 2)] + \
     [dict(mode=0, direction=d, small_frontier=sf) for d in (0, 1) for sf in (0, 1 << 30)] + \
     [dict(mode=0, direction=d, lds_bitmap=0) for d in (0, 2)] + \
-    [dict(mode=0, direction=d, bu_mapping=1) for d in (0, 2)]
+    [dict(mode=0, direction=d, bu_mapping=1) for d in (0, 2)] + \
+    [dict(mode=0, direction=d, td_plain=1 << 30, small_frontier=0) for d in (0, 1)] + \
+    [dict(mode=0, direction=0, td_plain=0)]
 
 
 def small_cases():
@@ -130,7 +132,13 @@ def test_hub_splitting_and_tuning_invariance(gpu):
                 # capacity) in levels that switch direction often, so the
                 # frontier bitmap is turned back into a queue with hubs in it
                 dict(hub_degree=1, chunk_edges=64, alpha=2, beta=200),
-                dict(hub_degree=8, chunk_edges=64, alpha=1, beta=1)]
+                dict(hub_degree=8, chunk_edges=64, alpha=1, beta=1),
+                # top-down claims by plain stores at every level (F_{d+1}
+                # read back from the depths, queued again when top-down
+                # follows), with hub chunk items in the input queues
+                dict(td_plain=1 << 30, small_frontier=0),
+                dict(td_plain=1 << 30, small_frontier=0, hub_degree=1, chunk_edges=64),
+                dict(td_plain=1 << 30, small_frontier=0, alpha=2, beta=200), dict(td_plain=0)]
     for src in srcs:
         ref = A.bfs(src)[0]
         for st in settings:
