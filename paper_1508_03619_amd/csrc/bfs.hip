@@ -43,6 +43,12 @@ struct SearchArgs {
 // is small and sends the answer with the release; when the small group
 // stops (a large level next, or the search done) it stores its state in
 // ctl->park and the level to rejoin at in ctl->resume.
+// Longest source list whose level 0 is folded into the initialisation.
+#ifndef GAP_FOLD_DEGREE
+#define GAP_FOLD_DEGREE 4096
+#endif
+constexpr int64_t kFoldDegree = GAP_FOLD_DEGREE;
+
 // Workgroups (of the block size in use) that run the small levels.
 // Measured on the 4096^2 grid, whose ~5,100 levels are nearly all small:
 // 1, 2, 4, 8, 16, 32, 64, 128 workgroups gave 250, 176, 131, 95, 74.2,
@@ -78,6 +84,35 @@ struct SmallDecision {
   }
 };
 
+// Level 0 folded into the initialisation (whole workgroup, after it has
+// initialised [lo, hi)): the source's neighbours in [lo, hi) get parent
+// `source` and depth 1 and are appended to F_1 (buffer set 1) as a top-down
+// step would append them; returns the workgroup's totals in thread 0.  Kept
+// out of line: it runs once per search, and inlined its registers would
+// count against the level loop's.
+template <int BLOCK, bool STATS>
+__device__ __forceinline__ Totals fold_level0(const SearchArgs &a, Stage<BLOCK> &st, int64_t lo, int64_t hi,
+                                           int64_t s_beg, int64_t s_end) {
+  __syncthreads();  // this workgroup's vertices are initialised
+  StepArgs s{a.g, a.parent, a.depth, a.Q, 0, a.ctl, nullptr, nullptr, nullptr, 0, a.p.hub, a.p.chunk};
+  step_begin<BLOCK>(s, st, false);
+  LaneAcc acc;
+  for (int64_t e0 = s_beg; e0 < s_end; e0 += BLOCK) {  // the same trip count on every thread
+    const int64_t e = e0 + threadIdx.x;
+    const int32_t v = e < s_end ? a.g.col[e] : -1;
+    const bool mine = v >= lo && v < hi;
+    int64_t degv = 0;
+    if (mine) {
+      degv = a.g.row_ptr[v + 1] - a.g.row_ptr[v];
+      a.parent[v] = a.source;
+      a.depth[v] = 1;
+    }
+    stage_append<BLOCK>(s, st, mine, v, degv, acc);
+  }
+  if (STATS && blockIdx.x == 0 && threadIdx.x == 0) acc.scanned += (unsigned long long)(s_end - s_beg);
+  return step_end<BLOCK>(s, st, acc);
+}
+
 template <int BLOCK, bool STATS>
 __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
   __shared__ Stage<BLOCK> st;
@@ -91,21 +126,65 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
   const bool small_enabled = a.p.small > 0 && nblocks > nsmall;
   const int64_t nwords_all = (a.g.n + kWave - 1) / kWave;
 
-  init_vertices(a.g, a.parent, a.depth, a.source, tid, nthreads);
+  // Level 0 expands F_0 = {source}.  When the source's list is short it is
+  // folded into the initialisation: workgroup b initialises the vertices of
+  // its own range [lo, hi) and then claims the source's neighbours in that
+  // range (no other workgroup writes them), appending F_1 as a top-down
+  // step would; the first barrier then ends level 0.
+  const int64_t s_beg = a.g.row_ptr[a.source], s_end = a.g.row_ptr[a.source + 1];
+  const bool fold = a.p.direction != GAP_DIR_BOTTOMUP && s_end > s_beg && s_end - s_beg <= kFoldDegree;
+  const unsigned long long t_init = (STATS || a.recs) ? rt_clock() : 0ull;
+  const int64_t per = ((a.g.n + 3) / 4 + nblocks - 1) / nblocks * 4;
+  const int64_t lo = (int64_t)blockIdx.x * per < a.g.n ? (int64_t)blockIdx.x * per : a.g.n;
+  const int64_t hi = lo + per < a.g.n ? lo + per : a.g.n;
+  init_vertices_range<BLOCK>(a.g, a.parent, a.depth, a.source, lo, hi);
   if (a.ctl_clear) {  // no search uses it now: the one before this has finished with it
     uint32_t *w = reinterpret_cast<uint32_t *>(a.ctl_clear);
     for (int64_t i = tid; i < (int64_t)(sizeof(Ctl) / sizeof(uint32_t)); i += nthreads) w[i] = 0u;
   }
   Totals part = {};
-  if (tid == 0) part = init_source(a.g, a.Q, a.ctl, a.source, a.p.hub, a.p.chunk);
-  if (!grid_sync(a.ctl, nblocks, part, 0, 0, a.p.wait)) return;
-
   int32_t d = 0, dir = kTopDown;
   bool have_bm = false;
   int64_t mu = a.g.nnz, nf_prev = 0;
   int fsel = 0;
   bool small = false;     // this level runs on the small group
   bool bm_ready = false;  // F_d's bitmaps were read back at the end of a plain-claim level
+  if (fold) {
+    part = fold_level0<BLOCK, STATS>(a, st, lo, hi, s_beg, s_end);
+    if ((STATS || a.recs) && tid == 0 && a.max_recs > 0) {
+      DevLevelRec r = {};
+      r.level = 0;
+      r.direction = kTopDown;
+      r.frontier = 1;
+      r.frontier_edges = (unsigned long long)(s_end - s_beg);
+      r.t_start = t_init;
+      a.recs[0] = r;
+    }
+    mu -= s_end - s_beg;
+    const SmallDecision dec{a.g.n, mu, 1, (int64_t)a.p.small, kTopDown, 0, 0, 0,
+                            a.p, false, small_enabled};
+    int small_next = 0;
+    if (!grid_sync_x(a.ctl, main_barrier(a.ctl, a.p.wait), nblocks, part, 1, 1, dec, small_next))
+      return;
+    small_next = uni(small_next);
+    d = 1;
+    nf_prev = 1;
+    if (small_next && blockIdx.x >= nsmall) {
+      ParkState ps;
+      if (!park_wait(a.ctl, (unsigned int)d, ps, a.p.wait_park)) return;
+      d = uni(ps.level);
+      dir = uni(ps.dir);
+      have_bm = uni(ps.have_bm) != 0;
+      fsel = uni(ps.fsel);
+      mu = uni((int64_t)ps.mu);
+      nf_prev = uni((int64_t)ps.nf_prev);
+    } else {
+      small = small_next != 0;
+    }
+  } else {
+    if (tid == 0) part = init_source(a.g, a.Q, a.ctl, a.source, a.p.hub, a.p.chunk);
+    if (!grid_sync(a.ctl, nblocks, part, 0, 0, a.p.wait)) return;
+  }
   for (;;) {
     const Published &P = a.ctl->pub[d & 1];
     const int64_t nv = uni((int64_t)ld_agent(&P.t.nv));

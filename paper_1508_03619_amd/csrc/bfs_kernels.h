@@ -336,9 +336,13 @@ __device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &
 template <int BLOCK, bool STATS>
 __device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
                                  const int32_t (&v)[4], const int32_t (&u)[4]) {
+  // loads without branches: a load under a per-lane condition gets a block
+  // of its own that waits for it before the next load issues
   int32_t p[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) p[k] = v[k] >= 0 ? a.parent[v[k]] : 0;
+  for (int k = 0; k < 4; ++k) p[k] = a.parent[v[k] >= 0 ? v[k] : 0];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = v[k] >= 0 ? p[k] : 0;
   bool claimed[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -368,7 +372,7 @@ __device__ inline void td_plain4(const StepArgs &a, LaneAcc &acc, const int32_t 
                                  const int32_t (&u)[4]) {
   int32_t p[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) p[k] = v[k] >= 0 ? a.parent[v[k]] : 0;
+  for (int k = 0; k < 4; ++k) p[k] = a.parent[v[k] >= 0 ? v[k] : 0];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (v[k] >= 0 && p[k] < 0) {
@@ -415,7 +419,8 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int64_t e = e0 + k * kWave + lane;
-        v[k] = e < end ? a.g.col[e] : -1;
+        const int32_t x = a.g.col[e < end ? e : beg];
+        v[k] = e < end ? x : -1;
         u[k] = uu;
       }
       if constexpr (PLAIN)
@@ -434,15 +439,14 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
   for (unsigned long long gi = (unsigned long long)gwave; gi < ngroups;
        gi += (unsigned long long)nwaves) {
     const unsigned long long idx = gi * per + lane;
-    int32_t uo = -1;
-    int64_t beg = 0;
-    uint32_t deg = 0;
-    if ((unsigned long long)lane < per && idx < nq) {
-      const int h = seg_of(idx, st.qpre);
-      uo = qin[h * a.Q.n + (int64_t)(idx - st.qpre[h])];
-      beg = a.g.row_ptr[uo];
-      deg = (uint32_t)(a.g.row_ptr[uo + 1] - beg);
-    }
+    const bool has = (unsigned long long)lane < per && idx < nq;
+    const unsigned long long ix = has ? idx : gi * per;  // gi * per < nq: a valid entry
+    const int h = seg_of(ix, st.qpre);
+    const int32_t ur = qin[h * a.Q.n + (int64_t)(ix - st.qpre[h])];
+    const int64_t b0 = a.g.row_ptr[ur], b1 = a.g.row_ptr[ur + 1];
+    const int32_t uo = has ? ur : -1;
+    const int64_t beg = has ? b0 : 0;
+    const uint32_t deg = has ? (uint32_t)(b1 - b0) : 0u;
     uint32_t total;
     const uint32_t off = wave_excl_scan_u32(deg, total);
     for (uint32_t b = 0; b < total; b += 4 * kWave) {
@@ -463,7 +467,10 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
         ea[k] = e < total ? bj + (int64_t)(e - oj) : -1;
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = ea[k] >= 0 ? a.g.col[ea[k]] : -1;
+      for (int k = 0; k < 4; ++k) {
+        const int32_t x = a.g.col[ea[k] >= 0 ? ea[k] : 0];
+        v[k] = ea[k] >= 0 ? x : -1;
+      }
       if constexpr (PLAIN)
         td_plain4<STATS>(a, acc, v, u);
       else
@@ -500,10 +507,14 @@ struct FrontierBits {
   const uint64_t *lds;
   int64_t lw;
   const uint64_t *g;
+  // u < 0 (no entry) tests false; the load is issued for every lane (a
+  // flat load when the LDS copy is in use), with no branch around it
   __device__ __forceinline__ bool test(int32_t u) const {
-    const int64_t w = u >> 6;
-    const uint64_t word = w < lw ? lds[w] : g[w];
-    return (word >> (u & 63)) & 1ull;
+    const int32_t uu = u < 0 ? 0 : u;
+    const int64_t w = uu >> 6;
+    const uint64_t *p = w < lw ? lds + w : g + w;
+    const uint64_t word = *p;
+    return (u >= 0) & (((word >> (uu & 63)) & 1ull) != 0);
   }
 };
 
@@ -530,17 +541,17 @@ __device__ inline bool bu_round(const int32_t *__restrict__ col, const FrontierB
   for (int j = 0; j < J; ++j)
 #pragma unroll
     for (int q = 0; q < RR / 4; ++q) {
-      i32x4_a4 w = {-1, -1, -1, -1};
-      if (act[j] && 4 * q < rem[j]) w = *reinterpret_cast<const i32x4_a4 *>(col + e[j] + 4 * q);
+      const bool use = act[j] && 4 * q < rem[j];
+      const i32x4_a4 w = *reinterpret_cast<const i32x4_a4 *>(use ? col + e[j] + 4 * q : col);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) u[j][4 * q + k] = (act[j] && 4 * q + k < rem[j]) ? w[k] : -1;
+      for (int k = 0; k < 4; ++k) u[j][4 * q + k] = (use && 4 * q + k < rem[j]) ? w[k] : -1;
     }
   bool hit[J][RR];
 #pragma unroll
   for (int j = 0; j < J; ++j)
 #pragma unroll
     for (int k = 0; k < RR; ++k)
-      hit[j][k] = u[j][k] >= 0 && fb.test(u[j][k]);
+      hit[j][k] = fb.test(u[j][k]);
   bool more = false;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -757,11 +768,14 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
         }
         const uint64_t bw = (uint64_t)__shfl((long long)win, jw, kWave);
         const uint32_t ow = (uint32_t)__shfl((int)off, jw, kWave);
+        // the row offsets are loaded by every lane (vertex 0 for lanes that
+        // take nothing): no branch around the loads
+        const int64_t vv = gets ? (wbase + jw) * kWave + nth_set_bit(bw, r - ow) : 0;
+        const int64_t r0 = rp[vv], r1 = rp[vv + 1];
         if (gets) {
-          const int64_t vv = (wbase + jw) * kWave + nth_set_bit(bw, r - ow);
           v[j] = (int32_t)vv;
-          e[j] = rp[vv];
-          rem[j] = (int32_t)(rp[vv + 1] - e[j]);
+          e[j] = r0;
+          rem[j] = (int32_t)(r1 - r0);
           deg[j] = rem[j];
           fresh[j] = true;
           if (STATS) acc.unvisited += 1;
@@ -781,19 +795,29 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
     constexpr int RUN = GAP_BU_RUN;
     int32_t u[J][RUN];
     int32_t adv[J];
+    i32x4_a4 w[J][RUN / 4];
+    // every slot's loads first, then the entries (a use right after each
+    // load would make the next load wait for it)
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+      for (int q = 0; q < RUN / 4; ++q) {
+        const bool use = v[j] >= 0 && 4 * q < rem[j] && (q == 0 || !fresh[j]);
+        const int32_t *src = !use ? col
+                             : fresh[j] ? reinterpret_cast<const int32_t *>(a.g.head_in + v[j])
+                                        : col + e[j] + 4 * q;
+        w[j][q] = *reinterpret_cast<const i32x4_a4 *>(src);
+      }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const bool head = fresh[j];
       adv[j] = head ? 4 : RUN;
 #pragma unroll
       for (int q = 0; q < RUN / 4; ++q) {
-        i32x4_a4 w = {-1, -1, -1, -1};
-        if (v[j] >= 0 && 4 * q < rem[j] && (q == 0 || !head))
-          w = *reinterpret_cast<const i32x4_a4 *>(
-              head ? reinterpret_cast<const int32_t *>(a.g.head_in + v[j]) : col + e[j] + 4 * q);
+        const bool use = v[j] >= 0 && 4 * q < rem[j] && (q == 0 || !head);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          u[j][4 * q + k] = (v[j] >= 0 && 4 * q + k < rem[j] && 4 * q + k < adv[j]) ? w[k] : -1;
+          u[j][4 * q + k] = (use && 4 * q + k < rem[j] && 4 * q + k < adv[j]) ? w[j][q][k] : -1;
       }
       fresh[j] = false;
     }
@@ -802,7 +826,7 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
     for (int j = 0; j < J; ++j)
 #pragma unroll
       for (int k = 0; k < RUN; ++k)
-        hit[j][k] = u[j][k] >= 0 && fb.test(u[j][k]);
+        hit[j][k] = fb.test(u[j][k]);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       if (v[j] < 0) continue;
@@ -912,8 +936,9 @@ __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *pare
     for (int u = 0; u < kConvU; ++u) {
       const int64_t v = (w0 + u * nwaves) * kWave + lane;
       const bool in = w0 + u * nwaves < nwords && v < g.n;
-      p[u] = in ? parent[v] : 0;
-      dv[u] = in ? depth[v] : -1;
+      const int32_t pr = parent[in ? v : 0], dr = depth[in ? v : 0];
+      p[u] = in ? pr : 0;
+      dv[u] = in ? dr : -1;
     }
 #pragma unroll
     for (int u = 0; u < kConvU; ++u) {
@@ -962,16 +987,14 @@ __device__ inline void init_vertices(const DevGraph &g, int32_t *parent, int32_t
     int64_t r[kInitU][5];
 #pragma unroll
     for (int u = 0; u < kInitU; ++u) {
-      const int64_t q = q0 + u * nthreads;
-      if (q < n4) {
-        const longlong2 a = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q);
-        const longlong2 b = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q + 2);
-        r[u][0] = a.x;
-        r[u][1] = a.y;
-        r[u][2] = b.x;
-        r[u][3] = b.y;
-        r[u][4] = g.row_ptr[4 * q + 4];
-      }
+      const int64_t q = q0 + u * nthreads < n4 ? q0 + u * nthreads : q0;  // no branch around the loads
+      const longlong2 a = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q);
+      const longlong2 b = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q + 2);
+      r[u][0] = a.x;
+      r[u][1] = a.y;
+      r[u][2] = b.x;
+      r[u][3] = b.y;
+      r[u][4] = g.row_ptr[4 * q + 4];
     }
 #pragma unroll
     for (int u = 0; u < kInitU; ++u) {
@@ -990,6 +1013,56 @@ __device__ inline void init_vertices(const DevGraph &g, int32_t *parent, int32_t
     }
   }
   for (int64_t v = 4 * n4 + tid; v < g.n; v += nthreads) {
+    int32_t p = initial_parent(g.row_ptr[v + 1] - g.row_ptr[v]);
+    int32_t dd = -1;
+    if (v == source) {
+      p = source;
+      dd = 0;
+    }
+    parent[v] = p;
+    depth[v] = dd;
+  }
+}
+
+// init_vertices over the vertices [lo, hi) of one workgroup (all its
+// threads; lo a multiple of 4 for the 16-byte stores).
+template <int BLOCK>
+__device__ inline void init_vertices_range(const DevGraph &g, int32_t *parent, int32_t *depth,
+                                           int32_t source, int64_t lo, int64_t hi) {
+  constexpr int kInitU = 4;
+  const bool vec = ((reinterpret_cast<uintptr_t>(parent) | reinterpret_cast<uintptr_t>(depth) |
+                     reinterpret_cast<uintptr_t>(g.row_ptr)) & 15u) == 0 && (lo & 3) == 0;
+  const int64_t q_lo = vec ? lo / 4 : 0, q_hi = vec ? hi / 4 : 0;
+  for (int64_t q0 = q_lo + threadIdx.x; q0 < q_hi; q0 += kInitU * BLOCK) {
+    int64_t r[kInitU][5];
+#pragma unroll
+    for (int u = 0; u < kInitU; ++u) {
+      const int64_t q = q0 + u * BLOCK < q_hi ? q0 + u * BLOCK : q0;  // no branch around the loads
+      const longlong2 x = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q);
+      const longlong2 y = *reinterpret_cast<const longlong2 *>(g.row_ptr + 4 * q + 2);
+      r[u][0] = x.x;
+      r[u][1] = x.y;
+      r[u][2] = y.x;
+      r[u][3] = y.y;
+      r[u][4] = g.row_ptr[4 * q + 4];
+    }
+#pragma unroll
+    for (int u = 0; u < kInitU; ++u) {
+      const int64_t q = q0 + u * BLOCK;
+      if (q >= q_hi) break;
+      int4 p = make_int4(initial_parent(r[u][1] - r[u][0]), initial_parent(r[u][2] - r[u][1]),
+                         initial_parent(r[u][3] - r[u][2]), initial_parent(r[u][4] - r[u][3]));
+      int4 dd = make_int4(-1, -1, -1, -1);
+      const int64_t k = (int64_t)source - 4 * q;
+      if (k == 0) { p.x = source; dd.x = 0; }
+      if (k == 1) { p.y = source; dd.y = 0; }
+      if (k == 2) { p.z = source; dd.z = 0; }
+      if (k == 3) { p.w = source; dd.w = 0; }
+      reinterpret_cast<int4 *>(parent)[q] = p;
+      reinterpret_cast<int4 *>(depth)[q] = dd;
+    }
+  }
+  for (int64_t v = (vec ? 4 * q_hi : lo) + threadIdx.x; v < hi; v += BLOCK) {
     int32_t p = initial_parent(g.row_ptr[v + 1] - g.row_ptr[v]);
     int32_t dd = -1;
     if (v == source) {
@@ -1030,10 +1103,7 @@ __device__ inline void fixup_parents(int64_t n, int32_t *parent, int64_t tid, in
   for (int64_t q0 = tid; q0 < n4; q0 += kFixU * nthreads) {
     int4 x[kFixU];
 #pragma unroll
-    for (int u = 0; u < kFixU; ++u) {
-      const int64_t q = q0 + u * nthreads;
-      if (q < n4) x[u] = p4[q];
-    }
+    for (int u = 0; u < kFixU; ++u) x[u] = p4[q0 + u * nthreads < n4 ? q0 + u * nthreads : q0];
 #pragma unroll
     for (int u = 0; u < kFixU; ++u) {
       const int64_t q = q0 + u * nthreads;

@@ -275,6 +275,26 @@ def test_lds_frontier_bitmap(gpu):
         g.free()
 
 
+def test_bottom_up_mappings_repeated(gpu):
+    """Both bottom-up mappings, with and without the LDS bitmap copy and
+    plain-store claims, five times each on R-MAT 16: the sources include
+    one (34524) whose search has many vertices whose first frontier
+    neighbour is the seventh list entry (the second round of four), where
+    one build of the kernel once lost finds now and then."""
+    from paper_1508_03619_amd import inputs
+    el = inputs.rmat(16, 16, seed=55)
+    g, A = graph_pair(gpu, el.n, el.src, el.dst)
+    srcs = [int(x) for x in inputs.pick_sources(el, 2, seed=58)] + [34524]
+    for src in srcs:
+        ref = A.bfs(src)[0]
+        for lds, bu, tp in itertools.product((0, 1), (0, 1), (0, 8)):
+            say(f"repeated src={src} lds={lds} bu_mapping={bu} td_plain={tp}")
+            for rep in range(5):
+                parent, depth = device_bfs(gpu, g, src, params=dict(lds_bitmap=lds, bu_mapping=bu, td_plain=tp))
+                assert_valid(A, src, parent, depth, ref, what=f"lds={lds} bu={bu} td_plain={tp} rep {rep}")
+    g.free()
+
+
 def test_grid_road_like(gpu):
     from paper_1508_03619_amd import inputs
     el = inputs.grid(300, 200, seed=7)
