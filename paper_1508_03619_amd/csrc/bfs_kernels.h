@@ -333,24 +333,24 @@ __device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &
 // Tries the claims (v[k] for parent u[k], v[k] < 0 = no edge) of four edge
 // batches at once: the parent probes, then the CAS claims, are issued
 // back-to-back so their latencies overlap; then the winners are appended.
-template <int BLOCK, bool STATS>
+template <int BLOCK, bool STATS, int NK = 4>
 __device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
                                  const int32_t (&v)[4], const int32_t (&u)[4]) {
   // loads without branches: a load under a per-lane condition gets a block
   // of its own that waits for it before the next load issues
   int32_t p[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) p[k] = a.parent[v[k] >= 0 ? v[k] : 0];
+  for (int k = 0; k < NK; ++k) p[k] = a.parent[v[k] >= 0 ? v[k] : u[k]];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) p[k] = v[k] >= 0 ? p[k] : 0;
+  for (int k = 0; k < NK; ++k) p[k] = v[k] >= 0 ? p[k] : 0;
   bool claimed[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NK; ++k) {
     claimed[k] = false;
     if (v[k] >= 0 && p[k] < 0) claimed[k] = atomicCAS(&a.parent[v[k]], p[k], u[k]) == p[k];
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NK; ++k) {
     int64_t degv = 0;
     if (claimed[k]) {
       a.depth[v[k]] = a.d + 1;
@@ -367,19 +367,39 @@ __device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &a
 // neighbour, so the parent is valid and the depth the same.  Nothing is
 // appended: F_{d+1} is read back from the depths after the level's barrier
 // (convert_to_bitmaps with totals), which also counts it exactly once.
-template <bool STATS>
+template <bool STATS, int NK = 4>
 __device__ inline void td_plain4(const StepArgs &a, LaneAcc &acc, const int32_t (&v)[4],
                                  const int32_t (&u)[4]) {
   int32_t p[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) p[k] = a.parent[v[k] >= 0 ? v[k] : 0];
+  for (int k = 0; k < NK; ++k) p[k] = a.parent[v[k] >= 0 ? v[k] : u[k]];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NK; ++k) {
     if (v[k] >= 0 && p[k] < 0) {
       a.parent[v[k]] = u[k];
       a.depth[v[k]] = a.d + 1;
     }
     if (STATS && v[k] >= 0) acc.scanned += 1;
+  }
+}
+
+// Claims of a round of up to four edge batches, `left` edges from the
+// round's first (wave-uniform): a round of at most 64 edges (the common
+// case on small frontiers) probes and claims one batch, not four of which
+// three are empty.
+template <int BLOCK, bool STATS, bool PLAIN>
+__device__ inline void td_claims(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
+                                 const int32_t (&v)[4], const int32_t (&u)[4], int64_t left) {
+  if (left <= kWave) {
+    if constexpr (PLAIN)
+      td_plain4<STATS, 1>(a, acc, v, u);
+    else
+      td_claim4<BLOCK, STATS, 1>(a, st, acc, v, u);
+  } else {
+    if constexpr (PLAIN)
+      td_plain4<STATS>(a, acc, v, u);
+    else
+      td_claim4<BLOCK, STATS>(a, st, acc, v, u);
   }
 }
 
@@ -423,10 +443,7 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
         v[k] = e < end ? x : -1;
         u[k] = uu;
       }
-      if constexpr (PLAIN)
-        td_plain4<STATS>(a, acc, v, u);
-      else
-        td_claim4<BLOCK, STATS>(a, st, acc, v, u);
+      td_claims<BLOCK, STATS, PLAIN>(a, st, acc, v, u, end - e0);
     }
   }
   // Vertices per wave: up to 64, fewer when the frontier is small so that
@@ -449,32 +466,42 @@ __device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
     const uint32_t deg = has ? (uint32_t)(b1 - b0) : 0u;
     uint32_t total;
     const uint32_t off = wave_excl_scan_u32(deg, total);
+    // edge e of the combined range -> its owner u and its list entry (idle
+    // lanes, e >= total, take the last edge's entry, encoded -entry - 1)
+    auto locate = [&](uint32_t e_raw, int32_t &uk, int64_t &eak) {
+      const uint32_t e = e_raw < total ? e_raw : total - 1;
+      int j = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        uint32_t oc = __shfl(off, j + step, kWave);
+        if (oc <= e) j += step;
+      }
+      uk = __shfl(uo, j, kWave);
+      const int64_t bj = __shfl(beg, j, kWave);
+      const uint32_t oj = __shfl(off, j, kWave);
+      eak = e_raw < total ? bj + (int64_t)(e - oj) : -(bj + (int64_t)(e - oj)) - 1;
+    };
     for (uint32_t b = 0; b < total; b += 4 * kWave) {
       int32_t v[4], u[4];
       int64_t ea[4];
+      // a round of at most 64 edges locates and loads one batch only
+      const int nk = total - b <= (uint32_t)kWave ? 1 : 4;
+      locate(b + (uint32_t)lane, u[0], ea[0]);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t e = b + (uint32_t)(k * kWave + lane);
-        int j = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-          uint32_t oc = __shfl(off, j + step, kWave);
-          if (oc <= e) j += step;
+      for (int k = 1; k < 4; ++k) {
+        if (nk == 4) {
+          locate(b + (uint32_t)(k * kWave + lane), u[k], ea[k]);
+        } else {  // idle batches: batch 0's entry, so their loads touch its lines
+          u[k] = u[0];
+          ea[k] = ea[0] >= 0 ? -ea[0] - 1 : ea[0];
         }
-        u[k] = __shfl(uo, j, kWave);
-        const int64_t bj = __shfl(beg, j, kWave);
-        const uint32_t oj = __shfl(off, j, kWave);
-        ea[k] = e < total ? bj + (int64_t)(e - oj) : -1;
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int32_t x = a.g.col[ea[k] >= 0 ? ea[k] : 0];
+        const int32_t x = a.g.col[ea[k] >= 0 ? ea[k] : -ea[k] - 1];
         v[k] = ea[k] >= 0 ? x : -1;
       }
-      if constexpr (PLAIN)
-        td_plain4<STATS>(a, acc, v, u);
-      else
-        td_claim4<BLOCK, STATS>(a, st, acc, v, u);
+      td_claims<BLOCK, STATS, PLAIN>(a, st, acc, v, u, (int64_t)(total - b));
     }
   }
 }
@@ -507,16 +534,27 @@ struct FrontierBits {
   const uint64_t *lds;
   int64_t lw;
   const uint64_t *g;
+  int32_t spare;  // a vertex of this wave's own (see wave_spare_vertex)
   // u < 0 (no entry) tests false; the load is issued for every lane (a
   // flat load when the LDS copy is in use), with no branch around it
   __device__ __forceinline__ bool test(int32_t u) const {
-    const int32_t uu = u < 0 ? 0 : u;
+    const int32_t uu = u < 0 ? spare : u;
     const int64_t w = uu >> 6;
     const uint64_t *p = w < lw ? lds + w : g + w;
     const uint64_t word = *p;
     return (u >= 0) & (((word >> (uu & 63)) & 1ull) != 0);
   }
 };
+
+// A vertex id that depends only on the wave (waves spread 1024 vertices
+// apart): lanes that have nothing to load use it for their address, so the
+// loads of an idle lane touch a line of their own wave's instead of one line
+// every wave of the grid would share.
+template <int BLOCK>
+__device__ inline int32_t wave_spare_vertex(int64_t n) {
+  const uint64_t w = (uint64_t)blockIdx.x * (BLOCK / kWave) + threadIdx.x / kWave;
+  return (int32_t)((w * 1024ull) % (uint64_t)n);
+}
 
 // Copies the first lw words of F_d into LDS (whole workgroup, then a
 // workgroup barrier); lw = 0 keeps every probe on the global copy.
@@ -527,14 +565,15 @@ __device__ inline FrontierBits frontier_bits(const StepArgs &a, uint64_t *lfbm, 
   if (lw > nwords) lw = nwords;
   for (int64_t i = threadIdx.x; i < lw; i += BLOCK) lfbm[i] = a.fbm[i];
   if (lw) __syncthreads();
-  return FrontierBits{lfbm, lw, a.fbm};
+  return FrontierBits{lfbm, lw, a.fbm, wave_spare_vertex<BLOCK>(a.g.n)};
 }
 
 // One round over the J vertices of a lane: RR entries each from e[j] on.
 // Returns whether any of them is still searching.
 template <int J, int RR, bool STATS>
 __device__ inline bool bu_round(const int32_t *__restrict__ col, const FrontierBits &fb, bool (&act)[J],
-                                int64_t (&e)[J], int32_t (&rem)[J], int32_t (&pu)[J], LaneAcc &acc) {
+                                int64_t (&e)[J], int32_t (&rem)[J], int32_t (&pu)[J], LaneAcc &acc,
+                                int64_t spare_e) {
   static_assert(RR % 4 == 0, "runs are read 16 bytes at a time");
   int32_t u[J][RR];
 #pragma unroll
@@ -542,7 +581,7 @@ __device__ inline bool bu_round(const int32_t *__restrict__ col, const FrontierB
 #pragma unroll
     for (int q = 0; q < RR / 4; ++q) {
       const bool use = act[j] && 4 * q < rem[j];
-      const i32x4_a4 w = *reinterpret_cast<const i32x4_a4 *>(use ? col + e[j] + 4 * q : col);
+      const i32x4_a4 w = *reinterpret_cast<const i32x4_a4 *>(col + (use ? e[j] + 4 * q : spare_e));
 #pragma unroll
       for (int k = 0; k < 4; ++k) u[j][4 * q + k] = (use && 4 * q + k < rem[j]) ? w[k] : -1;
     }
@@ -589,6 +628,9 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
   const int lane = lane_id();
   const int64_t nwords = (a.g.n + kWave - 1) / kWave;
   const FrontierBits fb = frontier_bits<BLOCK>(a, lfbm, lw);
+  // list offset an idle lane reads (a valid 16-byte run: the column array
+  // has kColPad entries beyond its last list)
+  const int64_t spare_e = a.g.row_ptr_in[fb.spare];
   for (int64_t base = gwave * J; base < nwords; base += nwaves * J) {
     uint64_t vis[J];
     int64_t e[J];       // next adjacency entry
@@ -612,8 +654,9 @@ __device__ void bu_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64
       }
       degv[j] = rem[j];
     }
-    bool more = bu_round<J, 4, STATS>(a.g.col_in, fb, act, e, rem, pu, acc);
-    while (__ballot(more) != 0ull) more = bu_round<J, R2, STATS>(a.g.col_in, fb, act, e, rem, pu, acc);
+    bool more = bu_round<J, 4, STATS>(a.g.col_in, fb, act, e, rem, pu, acc, spare_e);
+    while (__ballot(more) != 0ull)
+      more = bu_round<J, R2, STATS>(a.g.col_in, fb, act, e, rem, pu, acc, spare_e);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const bool found = pu[j] >= 0;
@@ -770,7 +813,7 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
         const uint32_t ow = (uint32_t)__shfl((int)off, jw, kWave);
         // the row offsets are loaded by every lane (vertex 0 for lanes that
         // take nothing): no branch around the loads
-        const int64_t vv = gets ? (wbase + jw) * kWave + nth_set_bit(bw, r - ow) : 0;
+        const int64_t vv = gets ? (wbase + jw) * kWave + nth_set_bit(bw, r - ow) : (int64_t)fb.spare;
         const int64_t r0 = rp[vv], r1 = rp[vv + 1];
         if (gets) {
           v[j] = (int32_t)vv;
@@ -803,7 +846,7 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
 #pragma unroll
       for (int q = 0; q < RUN / 4; ++q) {
         const bool use = v[j] >= 0 && 4 * q < rem[j] && (q == 0 || !fresh[j]);
-        const int32_t *src = !use ? col
+        const int32_t *src = !use ? reinterpret_cast<const int32_t *>(a.g.head_in + fb.spare)
                              : fresh[j] ? reinterpret_cast<const int32_t *>(a.g.head_in + v[j])
                                         : col + e[j] + 4 * q;
         w[j][q] = *reinterpret_cast<const i32x4_a4 *>(src);
@@ -930,13 +973,15 @@ __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *pare
   // kConvU words per pass: all their loads are issued before the first
   // ballot waits, so a wave keeps 2 * kConvU loads in flight
   constexpr int kConvU = 4;
+  const int32_t spare = (int32_t)(((uint64_t)gwave * 1024ull) % (uint64_t)g.n);
   for (int64_t w0 = gwave; w0 < nwords; w0 += kConvU * nwaves) {
     int32_t p[kConvU], dv[kConvU];
 #pragma unroll
     for (int u = 0; u < kConvU; ++u) {
       const int64_t v = (w0 + u * nwaves) * kWave + lane;
       const bool in = w0 + u * nwaves < nwords && v < g.n;
-      const int32_t pr = parent[in ? v : 0], dr = depth[in ? v : 0];
+      const int64_t vl = in ? v : (int64_t)spare;
+      const int32_t pr = parent[vl], dr = depth[vl];
       p[u] = in ? pr : 0;
       dv[u] = in ? dr : -1;
     }
