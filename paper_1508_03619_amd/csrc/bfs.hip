@@ -300,7 +300,9 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
     }
     small = small_next != 0;
   }
-  fixup_parents(a.g.n, a.parent, tid, nthreads);
+  // every vertex with an out-list was reached (the frontiers' edges add up
+  // to nnz) and there is no other: no parent is left negative
+  if (!(mu == 0 && a.g.n_sinks == 0)) fixup_parents(a.g.n, a.parent, tid, nthreads);
   if (tid == 0) a.ctl->levels = d;
 }
 
@@ -636,7 +638,7 @@ gap_status run_bfs(const gap_graph *g, int32_t source, int32_t *parent, int32_t 
   }
   SearchArgs a{};
   a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->head_in, g->n, g->nnz,
-                 g->directed};
+                 g->directed, g->n_sinks};
   a.parent = parent;
   a.depth = depth ? depth : ws->depth_scratch;
   a.source = source;
@@ -815,7 +817,7 @@ gap_status run_bfs_noalloc(const gap_graph *g, int32_t source, int32_t *parent, 
   if (st != GAP_OK) return st;
   SearchArgs a{};
   a.g = DevGraph{g->row_ptr, g->col, g->row_ptr_in, g->col_in, g->head_in, g->n, g->nnz,
-                 g->directed};
+                 g->directed, g->n_sinks};
   a.parent = parent;
   a.depth = depth ? depth : reinterpret_cast<int32_t *>(base + L.depth);
   a.source = source;

@@ -106,19 +106,23 @@ __global__ void k_row_ptr(const uint64_t *__restrict__ ukeys, int64_t nnz, int64
   }
 }
 
+// out[0] = largest degree, out[1] = vertices of degree 0.
 __global__ void k_max_degree(const int64_t *__restrict__ row_ptr, int64_t n,
                              unsigned long long *out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  unsigned long long best = 0;
+  unsigned long long best = 0, zeros = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     unsigned long long d = (unsigned long long)(row_ptr[v + 1] - row_ptr[v]);
     best = d > best ? d : best;
+    zeros += d == 0;
   }
   for (int o = 32; o >= 1; o >>= 1) {
     unsigned long long t = __shfl_xor(best, o, kWave);
     best = t > best ? t : best;
+    zeros += __shfl_xor(zeros, o, kWave);
   }
   if (lane_id() == 0 && best) atomicMax(out, best);
+  if (lane_id() == 0 && zeros) atomicAdd(out + 1, zeros);
 }
 
 static int grid_for(int64_t items) {
@@ -150,7 +154,7 @@ struct DevBuf {
 static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int32_t *d_w,
                            int64_t n, int64_t m, int bits, int mode, hipStream_t stream,
                            int64_t **row_ptr_out, int32_t **col_out, int32_t **wt_out,
-                           int64_t *nnz_out, int64_t *maxdeg_out) {
+                           int64_t *nnz_out, int64_t *maxdeg_out, int64_t *zeros_out = nullptr) {
   const uint64_t mask = (1ull << bits) - 1ull;
   const uint64_t sentinel = (1ull << (2 * bits)) - 1ull;  // = a self-loop key, never kept
   const int64_t len = mode == 0 ? 2 * m : m;
@@ -158,9 +162,9 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int
   GAP_HIP(d_keys.alloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1)));
   GAP_HIP(d_sorted.alloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1)));
   GAP_HIP(d_bad.alloc(sizeof(int)));
-  GAP_HIP(d_maxdeg.alloc(sizeof(unsigned long long)));
+  GAP_HIP(d_maxdeg.alloc(2 * sizeof(unsigned long long)));
   GAP_HIP(hipMemsetAsync(d_bad.p, 0, sizeof(int), stream));
-  GAP_HIP(hipMemsetAsync(d_maxdeg.p, 0, sizeof(unsigned long long), stream));
+  GAP_HIP(hipMemsetAsync(d_maxdeg.p, 0, 2 * sizeof(unsigned long long), stream));
   int64_t nnz = 0;
   if (m > 0) {
     k_make_keys<<<grid_for(m), 256, 0, stream>>>(d_src, d_dst, m, n, bits, sentinel, mode,
@@ -253,8 +257,8 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int
   k_row_ptr<<<grid_for(nnz + 1), 256, 0, stream>>>(d_keys.as<uint64_t>(), nnz, n, bits, row_ptr);
   k_max_degree<<<grid_for(n), 256, 0, stream>>>(row_ptr, n, d_maxdeg.as<unsigned long long>());
   hipError_t le = hipGetLastError();
-  unsigned long long maxdeg = 0;
-  hipError_t ce = hipMemcpyAsync(&maxdeg, d_maxdeg.p, sizeof(maxdeg), hipMemcpyDeviceToHost,
+  unsigned long long deg_stats[2] = {0, 0};
+  hipError_t ce = hipMemcpyAsync(deg_stats, d_maxdeg.p, sizeof(deg_stats), hipMemcpyDeviceToHost,
                                  stream);
   hipError_t se = hipStreamSynchronize(stream);
   if (le != hipSuccess || ce != hipSuccess || se != hipSuccess) {
@@ -267,7 +271,8 @@ static gap_status csr_pass(const int32_t *d_src, const int32_t *d_dst, const int
   *col_out = col;
   if (wt_out) *wt_out = wt;
   *nnz_out = nnz;
-  *maxdeg_out = (int64_t)maxdeg;
+  *maxdeg_out = (int64_t)deg_stats[0];
+  if (zeros_out) *zeros_out = (int64_t)deg_stats[1];
   return GAP_OK;
 }
 
@@ -341,7 +346,8 @@ gap_status build_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *ds
   // out-lists (top-down) and the in-lists (bottom-up)
   gap_status st = csr_pass(d_src.as<int32_t>(), d_dst.as<int32_t>(),
                            weights ? d_w.as<int32_t>() : nullptr, n, m, bits, directed ? 1 : 0,
-                           stream, &g->row_ptr, &g->col, &g->wt, &g->nnz, &g->max_degree);
+                           stream, &g->row_ptr, &g->col, &g->wt, &g->nnz, &g->max_degree,
+                           &g->n_sinks);
   if (st != GAP_OK) {
     delete g;
     return st;

@@ -37,6 +37,7 @@ struct DevGraph {
   int64_t n;
   int64_t nnz;
   int32_t directed;
+  int64_t n_sinks;            // vertices with no out-list entry
 };
 
 // Level totals reduced across the grid.

@@ -23,6 +23,7 @@ struct gap_graph {
   int64_t *row_ptr_in;  // device in-lists; the same arrays as row_ptr/col when undirected
   int32_t *col_in;
   int64_t max_degree;
+  int64_t n_sinks;      // vertices with no out-list entry
   int32_t *wt;          // device int32[nnz] out-list weights, or NULL (every weight 1)
   int32_t max_weight;   // 1 when unweighted
   // First four entries of every list, one 16-byte record per vertex (-1 past
