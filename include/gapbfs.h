@@ -452,6 +452,17 @@ typedef struct gap_params {
                             totals are then read back from the depths by one
                             pass over the vertices; 0 = every level claims by
                             compare-and-swap.  Default 8. */
+  int32_t coop_launch;   /* grid-barrier kernels (persistent searches,
+                            batches, serving, shortest paths): 0 = ordinary
+                            launches sized to be resident, ordered by the
+                            library's per-device launch ring so that at most
+                            grid_split of them run at once (the default;
+                            ~15 us less between consecutive searches), 1 =
+                            cooperative launches (the runtime checks
+                            residency; use when other software on the same
+                            GPU launches its own grid-barrier kernels).  A
+                            broken residency assumption ends in GAP_ETIMEOUT
+                            from the bounded waits, not in a hang. */
 } gap_params;
 
 /* Process-wide parameters (copied).  Invalid values -> GAP_EINVAL. */

@@ -141,9 +141,10 @@ gap_status coop_end(int dev, hipStream_t s, CoopOrder *o) {
   return GAP_OK;
 }
 
-// Private (scratch) bytes per lane of a kernel, cached.  A kernel that
-// spills may have fewer waves resident than its occupancy says (scratch is
-// granted per wave), so an ordinary launch cannot rely on residency.
+// Private (scratch) bytes per lane of a kernel, cached.  Scratch is granted
+// per wave: a grid whose waves need a large total may have fewer waves
+// resident than its occupancy says, so an ordinary launch relies on
+// residency only below kOrdinaryScratchBytes for the whole grid.
 static size_t kernel_scratch(const void *kern) {
   static std::mutex mu;
   static std::map<const void *, size_t> cache;
@@ -158,8 +159,10 @@ static size_t kernel_scratch(const void *kern) {
   return bytes;
 }
 
+constexpr size_t kOrdinaryScratchBytes = 256ull << 20;
+
 gap_status launch_resident(const void *kern, int max_grid, int block, size_t shmem, void **kargs,
-                           int split, const DeviceInfo *di, hipStream_t s, int *grid_out) {
+                           int split, int coop, const DeviceInfo *di, hipStream_t s, int *grid_out) {
   int grid = max_grid;
   if (split > 1) {
     const int x = di->xccs;
@@ -167,7 +170,12 @@ gap_status launch_resident(const void *kern, int max_grid, int block, size_t shm
     if (grid < x) grid = max_grid / split;
     if (grid < 1) grid = 1;
   }
-  if (split > 1 && kernel_scratch(kern) == 0) {
+  const size_t scratch = kernel_scratch(kern) * (size_t)block * (size_t)grid;
+  if (!coop && scratch <= kOrdinaryScratchBytes) {
+    // an ordinary launch: the grid is sized to be resident, and the
+    // device's launch ring (coop_begin) keeps the library's grid-barrier
+    // kernels from running more than `split` at once; the barriers' bounded
+    // waits turn a broken assumption into GAP_ETIMEOUT
     GAP_HIP(hipLaunchKernel(kern, dim3(grid), dim3(block), kargs, shmem, s));
   } else {
     // the runtime checks residency (and such launches do not overlap)
@@ -201,6 +209,7 @@ static gap_params default_params() {
   p.batch_words = 4;
   p.serve_window_us = 5000;
   p.td_plain = 8;
+  p.coop_launch = 0;
   return p;
 }
 
@@ -262,6 +271,10 @@ gap_status params_check(const gap_params &p) {
   }
   if (p.serve_window_us < 0) {
     set_error("params: serve_window_us must be >= 0");
+    return GAP_EINVAL;
+  }
+  if (p.coop_launch != 0 && p.coop_launch != 1) {
+    set_error("params: coop_launch must be 0 or 1");
     return GAP_EINVAL;
   }
   if (p.td_plain < 0) {

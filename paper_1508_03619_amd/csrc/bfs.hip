@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kLevelBlock) void k_dd_fixup(DDArgs *A) {
 
 template <int BLOCK, bool STATS>
 static gap_status launch_persistent(const SearchArgs &a, const DeviceInfo *di, int blocks_per_cu,
-                                    int split, int lds_bitmap, hipStream_t stream) {
+                                    int split, int coop, int lds_bitmap, hipStream_t stream) {
   auto kern = k_bfs_persistent<BLOCK, STATS>;
   SearchArgs args = a;
   // the frontier bitmap goes to LDS next to the static staging: all of it
@@ -480,8 +480,8 @@ static gap_status launch_persistent(const SearchArgs &a, const DeviceInfo *di, i
   }
   if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
   void *kargs[] = {&args};
-  return launch_resident((const void *)kern, per_cu * di->cus, BLOCK, shmem, kargs, split, di,
-                         stream, nullptr);
+  return launch_resident((const void *)kern, per_cu * di->cus, BLOCK, shmem, kargs, split, coop,
+                         di, stream, nullptr);
 }
 
 template <bool STATS>
@@ -489,13 +489,13 @@ static gap_status dispatch_persistent(const SearchArgs &a, const DeviceInfo *di,
                                       const gap_params &p, hipStream_t stream) {
   switch (p.block) {
     case 256:
-      return launch_persistent<256, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.lds_bitmap,
+      return launch_persistent<256, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.coop_launch, p.lds_bitmap,
                                            stream);
     case 512:
-      return launch_persistent<512, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.lds_bitmap,
+      return launch_persistent<512, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.coop_launch, p.lds_bitmap,
                                            stream);
     default:
-      return launch_persistent<1024, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.lds_bitmap,
+      return launch_persistent<1024, STATS>(a, di, p.blocks_per_cu, p.grid_split, p.coop_launch, p.lds_bitmap,
                                             stream);
   }
 }

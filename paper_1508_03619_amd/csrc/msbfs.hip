@@ -632,7 +632,7 @@ __global__ __launch_bounds__(kOutBlock) void k_ms_output(MsArgs a, int64_t nword
 // ---- host side ------------------------------------------------------------------------
 
 template <int W>
-static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int split, bool stats, int64_t ntiles,
+static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int split, int coop, bool stats, int64_t ntiles,
                             const int64_t *tile_base, hipStream_t stream) {
   auto kern = stats ? k_msbfs<W, true> : k_msbfs<W, false>;
   int per_cu = 0;
@@ -644,8 +644,8 @@ static gap_status launch_ms(const MsArgs &a, const DeviceInfo *di, int split, bo
   MsArgs args = a;
   void *kargs[] = {&args};
   // 1024-thread workgroups, one per CU
-  gap_status st = launch_resident((const void *)kern, di->cus, kMsBlock, 0, kargs, split, di, stream,
-                                  nullptr);
+  gap_status st = launch_resident((const void *)kern, di->cus, kMsBlock, 0, kargs, split, coop, di,
+                                  stream, nullptr);
   if (st != GAP_OK) return st;
   int64_t blocks = (ntiles + kOutBlock / kWave - 1) / (kOutBlock / kWave);
   if (blocks > (int64_t)di->cus * 8) blocks = (int64_t)di->cus * 8;
@@ -798,9 +798,9 @@ gap_status run_bfs_batch(const gap_graph *const *graphs, int32_t num_graphs,
   st = coop_begin(dev, stream, p.grid_split, &order);
   if (st != GAP_OK) return st;
   switch (W) {
-    case 1: st = launch_ms<1>(a, di, p.grid_split, want_stats, ntiles, d_tile_base, stream); break;
-    case 2: st = launch_ms<2>(a, di, p.grid_split, want_stats, ntiles, d_tile_base, stream); break;
-    default: st = launch_ms<4>(a, di, p.grid_split, want_stats, ntiles, d_tile_base, stream); break;
+    case 1: st = launch_ms<1>(a, di, p.grid_split, p.coop_launch, want_stats, ntiles, d_tile_base, stream); break;
+    case 2: st = launch_ms<2>(a, di, p.grid_split, p.coop_launch, want_stats, ntiles, d_tile_base, stream); break;
+    default: st = launch_ms<4>(a, di, p.grid_split, p.coop_launch, want_stats, ntiles, d_tile_base, stream); break;
   }
   gap_status st2 = coop_end(dev, stream, &order);
   if (st != GAP_OK) return st;

@@ -160,17 +160,20 @@ gap_status coop_end_existing(int dev, hipStream_t s, CoopOrder *o);
 
 // Launches a kernel whose workgroups wait on each other (grid barriers).
 // max_grid is the largest grid that is resident at once on the whole
-// device.  split = 1: a cooperative launch of max_grid workgroups (the
-// runtime checks residency; cooperative launches do not run concurrently).
-// split = k > 1: an ordinary launch of max_grid / k workgroups rounded down
-// to a multiple of the die count, so each die receives the same number;
-// with at most k such grids in flight (coop_begin) their sum fits on every
-// die at once.  A kernel that uses scratch is still launched cooperatively
-// (its waves may be limited by scratch, not by occupancy).  Waits inside
-// the kernels are bounded, so a broken residency assumption ends in
+// device; split = k > 1 takes max_grid / k workgroups rounded down to a
+// multiple of the die count, so each die receives the same number.  coop =
+// 0: an ordinary launch -- with at most k such grids in flight (the ring of
+// coop_begin, which every grid-barrier kernel of the library goes through)
+// their sum fits on every die at once, and any other kernel finishes on its
+// own; a kernel whose waves need more than kOrdinaryScratchBytes of scratch
+// in all is still launched cooperatively (its waves may be limited by
+// scratch, not by occupancy).  coop = 1: a cooperative launch (the runtime
+// checks residency; cooperative launches do not run concurrently, and each
+// costs ~15 us more between consecutive searches).  Waits inside the
+// kernels are bounded, so a broken residency assumption ends in
 // GAP_ETIMEOUT rather than a hang.
 gap_status launch_resident(const void *kern, int max_grid, int block, size_t shmem, void **kargs,
-                           int split, const DeviceInfo *di, hipStream_t s, int *grid_out);
+                           int split, int coop, const DeviceInfo *di, hipStream_t s, int *grid_out);
 
 gap_params params_current();
 gap_status params_check(const gap_params &p);

@@ -624,7 +624,7 @@ gap_status server_launch(gap_server *s) {
       st = GAP_EDEVICE;
     } else if (e == hipSuccess) {
       void *kargs[] = {&a};
-      st = launch_resident((const void *)k_serve, di->cus, kSrvBlock, 0, kargs, p.grid_split, di,
+      st = launch_resident((const void *)k_serve, di->cus, kSrvBlock, 0, kargs, p.grid_split, p.coop_launch, di,
                            s->stream, nullptr);
     }
   }

@@ -456,8 +456,8 @@ gap_status run_sssp(const gap_graph *g, int32_t source, uint32_t *dist, uint32_t
   CoopOrder order;
   st = coop_begin(g->device, stream, 1, &order);
   if (st != GAP_OK) return st;
-  st = launch_resident((const void *)kern, per_cu * di->cus, kSpBlock, 0, kargs, 1, di, stream,
-                       nullptr);
+  st = launch_resident((const void *)kern, per_cu * di->cus, kSpBlock, 0, kargs, 1,
+                       params_current().coop_launch, di, stream, nullptr);
   gap_status st2 = coop_end(g->device, stream, &order);
   if (st != GAP_OK) return st;
   if (st2 != GAP_OK) return st2;

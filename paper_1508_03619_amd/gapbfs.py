@@ -41,7 +41,8 @@ class _Params(ctypes.Structure):
                 ("grid_split", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
                 ("lds_bitmap", ctypes.c_int32), ("wait_limit_us", ctypes.c_int32),
                 ("bu_mapping", ctypes.c_int32), ("batch_words", ctypes.c_int32),
-                ("serve_window_us", ctypes.c_int32), ("td_plain", ctypes.c_int32)]
+                ("serve_window_us", ctypes.c_int32), ("td_plain", ctypes.c_int32),
+                ("coop_launch", ctypes.c_int32)]
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_]

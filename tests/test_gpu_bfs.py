@@ -16,7 +16,7 @@ SCHEDULES = [dict(mode=m, direction=d) for m in (0, 1, 2) for d in (0, 1, 2)] + 
     [dict(mode=0, direction=d, lds_bitmap=0) for d in (0, 2)] + \
     [dict(mode=0, direction=d, bu_mapping=1) for d in (0, 2)] + \
     [dict(mode=0, direction=d, td_plain=1 << 30, small_frontier=0) for d in (0, 1)] + \
-    [dict(mode=0, direction=0, td_plain=0)]
+    [dict(mode=0, direction=0, td_plain=0), dict(mode=0, direction=0, coop_launch=1)]
 
 
 def small_cases():
@@ -195,20 +195,22 @@ def test_two_streams_concurrently(gpu):
         assert_valid(A, src, p.cpu().numpy(), d.cpu().numpy())
 
 
-@pytest.mark.parametrize("split", [2, 3, 4])
-def test_grid_split_streams_overlap(gpu, split):
+@pytest.mark.parametrize("split,coop", [(1, 0), (2, 0), (3, 0), (4, 0), (2, 1)])
+def test_grid_split_streams_overlap(gpu, split, coop):
     """With grid_split = k, k persistent launches (single and batched) run at
-    once on k streams; every result stays exact."""
+    once on k streams (ordinary launches ordered by the device's launch
+    ring; with coop_launch = 1 cooperative launches, which do not overlap);
+    every result stays exact."""
     import torch
     from paper_1508_03619_amd import inputs
     el = inputs.rmat(14, 16, seed=43)
     g, A = graph_pair(gpu, el.n, el.src, el.dst)
     srcs = [int(x) for x in inputs.pick_sources(el, 24, seed=44)]
     saved = gpu.get_params()
-    gpu.set_params(grid_split=split)
+    gpu.set_params(grid_split=split, coop_launch=coop)
     streams = [torch.cuda.Stream() for _ in range(split + 1)]
     outs = []
-    say(f"grid_split={split}")
+    say(f"grid_split={split} coop_launch={coop}")
     try:
         for i, src in enumerate(srcs):
             st = streams[i % len(streams)]
