@@ -695,6 +695,11 @@ def main():
                     help="comma list of extra legs reported in detail: strict, serving, directed, "
                          "bc, sssp, cc, grid4096, rmat24, mixed, or all")
     ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--profile-levels", type=int, default=0, metavar="K",
+                    help="for rocprofv3 counter runs: K sources per graph searched with the "
+                         "per-level schedule (one launch per step), each after a statistics run "
+                         "whose records are printed as JSON lines, so rocprof_summary levels can "
+                         "attribute counters to levels")
     ap.add_argument("--profile-leg", action="store_true",
                     help="for rocprofv3 counter runs: a copy of known size, then one search per "
                          "source, no timing and no JSON")
@@ -718,6 +723,24 @@ def main():
     for name in args.graphs.split(","):
         el = inputs.workload(name)
         cases.append(GraphCase(name, el, gb, torch, args.sources, inputs.SOURCE_SEEDS[name]))
+
+    if args.profile_levels:
+        a = torch.empty(PROFILE_COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            gb.stream_copy(b, a, PROFILE_COPY_BYTES)
+        torch.cuda.synchronize()
+        del a, b
+        for c in cases:
+            for s in c.sources[:args.profile_levels]:
+                recs = gb.bfs(c.g, int(s), c.parent, c.depth, params={"mode": 1}, stats=True)
+                gb.bfs(c.g, int(s), c.parent, c.depth, params={"mode": 1})
+                torch.cuda.synchronize()
+                keep = ("direction", "frontier", "frontier_edges", "claimed", "scanned", "unvisited")
+                print("LEVELS " + json.dumps({"graph": c.name, "n": c.g.n, "source": int(s),
+                                              "levels": [[r[k] for k in keep] for r in recs]}), flush=True)
+        log("profile levels done")
+        return
 
     if args.profile_leg:
         a = torch.empty(PROFILE_COPY_BYTES // 4, dtype=torch.int32, device="cuda")

@@ -6,6 +6,8 @@ Usage:
          <write_counter_collection.csv> <out.json> --kernel k_bfs_persistent --copy-bytes N --cmd "..."
   python -m paper_1508_03619_amd.rocprof_summary counters <counter_collection.csv>... --out <out.txt>
          --kernel k_bfs_persistent --kernel k_msbfs --cmd "..."
+  python -m paper_1508_03619_amd.rocprof_summary levels <fetch.csv> <write.csv> <bench log> <out.txt>
+         --copy-bytes N --cmd "..."
 
 The traffic summary scales the counters of the search kernel by the ratio
 (known bytes / counted bytes) measured on the streaming-copy kernel in the
@@ -46,6 +48,113 @@ def hash_line(kernels) -> str:
 
 def short(name: str) -> str:
     return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+
+
+def _dispatches(path):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def _copy_scale(rows, copy_bytes):
+    v = [float(r["Counter_Value"]) for r in rows if "k_stream_copy" in r["Kernel_Name"]]
+    return copy_bytes / (sum(v) / len(v))
+
+
+def _searches(rows):
+    """Groups the per-level schedule's dispatches into searches: k_dd_init,
+    then (k_dd_convert, k_dd_step, k_dd_publish) per level, then k_dd_fixup.
+    Returns the searches run without statistics, each as a dict of
+    (fetch-or-write value, duration ns) lists."""
+    out, cur = [], None
+    for r in rows:
+        k = r["Kernel_Name"]
+        if "k_dd_" not in k:
+            continue
+        v = float(r["Counter_Value"])
+        t = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        if "k_dd_init" in k:
+            cur = {"init": (v, t), "convert": [], "step": [], "publish": [], "fixup": None, "stats": False}
+            out.append(cur)
+        elif cur is None:
+            continue
+        elif "k_dd_convert" in k:
+            cur["convert"].append((v, t))
+        elif "k_dd_step" in k:
+            cur["step"].append((v, t))
+            cur["stats"] = cur["stats"] or "<true>" in k
+        elif "k_dd_publish" in k:
+            cur["publish"].append((v, t))
+        elif "k_dd_fixup" in k:
+            cur["fixup"] = (v, t)
+    return [s for s in out if not s["stats"] and s["fixup"] is not None]
+
+
+def level_alg_bytes(rec, prev_dir, n):
+    """Algorithmic bytes of one level record [direction, frontier,
+    frontier_edges, claimed, scanned, unvisited] (the search's byte model):
+    returns (bytes of the step, bytes of the conversion before it)."""
+    d, f, mf, cl, sc, un = rec
+    if d == 1:
+        conv = 20 * f + n // 8 if prev_dir == 2 else 0
+        return 20 * f + 8 * mf + 12 * cl, conv
+    conv = 4 * f + n // 8 if prev_dir == 1 else 0
+    return 16 * un + 4 * sc + 3 * n // 8 + 8 * cl, conv
+
+
+def levels(args):
+    """Per-level attribution of FETCH_SIZE / WRITE_SIZE and time for the
+    per-level schedule (one launch per step)."""
+    recs = [json.loads(l[len("LEVELS "):]) for l in open(args.log) if l.startswith("LEVELS ")]
+    F, W = _dispatches(args.fetch), _dispatches(args.write)
+    fs, ws = _copy_scale(F, args.copy_bytes), _copy_scale(W, args.copy_bytes)
+    sf, sw = _searches(F), _searches(W)
+    if not (len(sf) == len(sw) == len(recs)):
+        raise SystemExit(f"{len(sf)} fetch searches, {len(sw)} write searches, {len(recs)} records")
+    cats = {}
+
+    def add(cat, fv, wv, t, alg):
+        c = cats.setdefault(cat, [0, 0.0, 0.0, 0, 0])
+        c[0] += 1
+        c[1] += fv * fs
+        c[2] += wv * ws
+        c[3] += t
+        c[4] += alg
+
+    for s_f, s_w, rec in zip(sf, sw, recs):
+        n = rec["n"]
+        g = rec["graph"]
+        lv = rec["levels"]
+        if len(s_f["step"]) != len(lv):
+            raise SystemExit(f"{g} source {rec['source']}: {len(s_f['step'])} steps, {len(lv)} records")
+        add(f"{g} init", s_f["init"][0], s_w["init"][0], s_f["init"][1], 16 * n + 8)
+        prev, first_bu = 1, True
+        for i, r in enumerate(lv):
+            step_alg, conv_alg = level_alg_bytes(r, prev, n)
+            if r[0] == 1:
+                cat = f"{g} top-down, m_f <= 32768" if r[2] <= 32768 else f"{g} top-down, m_f > 32768"
+            else:
+                cat = f"{g} bottom-up, first" if first_bu else f"{g} bottom-up, later"
+                first_bu = False
+            add(cat, s_f["step"][i][0], s_w["step"][i][0], s_f["step"][i][1], step_alg)
+            if conv_alg:
+                add(f"{g} conversion", s_f["convert"][i][0], s_w["convert"][i][0], s_f["convert"][i][1], conv_alg)
+            add(f"{g} level boundary (publish)", s_f["publish"][i][0], s_w["publish"][i][0], s_f["publish"][i][1], 0)
+            prev = r[0]
+        add(f"{g} final pass", s_f["fixup"][0], s_w["fixup"][0], s_f["fixup"][1], 8 * n)
+    lines = ["# per-level attribution of counted traffic and time, per-level schedule (mode 1)",
+             f"# command: {args.cmd}", hash_line(["k_bfs_persistent"]),
+             f"# {len(recs)} searches; fetch scale {fs:.1f} B/unit, write scale {ws:.1f} B/unit (copy kernel)",
+             "# columns are per occurrence: MB fetched, MB written, algorithmic MB, counted/algorithmic, us",
+             "", f"{'category':44s} {'count':>5s} {'fetch MB':>9s} {'write MB':>9s} {'alg MB':>8s} "
+             f"{'ratio':>6s} {'us':>8s}"]
+    for cat in sorted(cats):
+        c, fb, wb, t, alg = cats[cat]
+        ratio = (fb + wb) / alg if alg else float("nan")
+        lines.append(f"{cat:44s} {c:5d} {fb / c / 1e6:9.2f} {wb / c / 1e6:9.2f} {alg / c / 1e6:8.2f} "
+                     f"{ratio:6.2f} {t / c / 1e3:8.1f}")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def stats(args):
@@ -160,8 +269,15 @@ def main():
     c.add_argument("--out", required=True)
     c.add_argument("--kernel", action="append", default=[])
     c.add_argument("--cmd", default="")
+    lv = sub.add_parser("levels")
+    lv.add_argument("fetch")
+    lv.add_argument("write")
+    lv.add_argument("log", help="bench.py --profile-levels output (its LEVELS lines)")
+    lv.add_argument("out")
+    lv.add_argument("--copy-bytes", type=float, required=True)
+    lv.add_argument("--cmd", default="")
     a = ap.parse_args()
-    {"stats": stats, "traffic": traffic, "counters": counters}[a.what](a)
+    {"stats": stats, "traffic": traffic, "counters": counters, "levels": levels}[a.what](a)
 
 
 if __name__ == "__main__":

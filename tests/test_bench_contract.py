@@ -61,3 +61,66 @@ def test_batch_algorithmic_bytes_model():
               "scanned": 900, "unvisited": 500}
         want_bu = 24 * W * n + 16 * 500 + 16 * W * 500 + 900 * (4 + 8 * W)
         assert bench.batch_algorithmic_bytes([td, bu], n, lanes) == base + want_td + want_bu
+
+
+def test_level_attribution_matches_the_byte_model(tmp_path):
+    """rocprof_summary levels: dispatches of the per-level schedule grouped
+    into searches (statistics runs skipped), counters scaled by the copy
+    kernel, and per-level algorithmic bytes that add up (with the
+    initialisation and the final pass) to bench.algorithmic_bytes."""
+    import csv
+    import json
+    import types
+    import bench
+    from paper_1508_03619_amd import rocprof_summary as rs
+    n = 1000
+    recs = [[1, 1, 5, 5, 5, 0], [1, 5, 40, 30, 40, 0], [2, 30, 500, 600, 900, 700],
+            [2, 600, 100, 10, 12, 11], [1, 10, 20, 0, 20, 0]]
+    as_dicts = [dict(zip(("direction", "frontier", "frontier_edges", "claimed", "scanned", "unvisited"), r))
+                for r in recs]
+    total = 16 * n + 8 + 8 * n
+    prev = 1
+    for r in recs:
+        step, conv = rs.level_alg_bytes(r, prev, n)
+        total += step + conv
+        prev = r[0]
+    assert total == bench.algorithmic_bytes(as_dicts, n)
+
+    def rows(value):
+        out, did = [], 0
+        def emit(name, v, t=1000):
+            nonlocal did
+            did += 1
+            out.append({"Dispatch_Id": did, "Kernel_Name": name, "Counter_Value": v,
+                        "Start_Timestamp": 0, "End_Timestamp": t})
+        emit("gap::k_stream_copy(...)", 1024)
+        for stats in (True, False):  # a statistics run, then the plain run
+            emit("void gap::k_dd_init(gap::DDArgs*)", value)
+            emit("void gap::k_dd_publish<%s>(gap::DDArgs*)" % str(stats).lower(), 0)
+            for _ in recs:
+                emit("void gap::k_dd_convert(gap::DDArgs*)", value)
+                emit("void gap::k_dd_step<%s>(gap::DDArgs*)" % str(stats).lower(), value)
+                emit("void gap::k_dd_publish<%s>(gap::DDArgs*)" % str(stats).lower(), 0)
+            emit("void gap::k_dd_fixup(gap::DDArgs*)", value)
+        return out
+
+    for name, v in (("f.csv", 2), ("w.csv", 1)):
+        with open(tmp_path / name, "w", newline="") as fh:
+            w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Value",
+                                               "Start_Timestamp", "End_Timestamp"])
+            w.writeheader()
+            w.writerows(rows(v))
+    (tmp_path / "b.log").write_text("x\nLEVELS " + json.dumps({"graph": "g", "n": n, "source": 3,
+                                                               "levels": recs}) + "\n")
+    out = tmp_path / "o.txt"
+    rs.levels(types.SimpleNamespace(fetch=str(tmp_path / "f.csv"), write=str(tmp_path / "w.csv"),
+                                    log=str(tmp_path / "b.log"), out=str(out), copy_bytes=1024 * 8e6,
+                                    cmd="test"))
+    text = out.read_text()
+    # copy kernel: 1024 units for 8.192e9 bytes -> 8e6 bytes per unit; a step
+    # of 2 units fetched is 16 MB, of 1 unit written 8 MB
+    line = [l for l in text.splitlines() if l.startswith("g bottom-up, first")][0].split()
+    assert line[3:6] == ["1", "16.00", "8.00"], line  # one occurrence, MB fetched, MB written
+    td = [l for l in text.splitlines() if l.startswith("g top-down, m_f <= 32768")][0].split()
+    assert td[5] == "3", td  # three small top-down levels
+    assert "g top-down, m_f <= 32768" in text and "g conversion" in text and "g final pass" in text
