@@ -397,7 +397,9 @@ typedef struct gap_params {
   int32_t direction;     /* GAP_DIR_* */
   int32_t alpha;         /* top-down -> bottom-up when m_f > m_u / alpha */
   int32_t beta;          /* bottom-up -> top-down when n_f < n / beta and
-                            the frontier shrank */
+                            the frontier shrank (default 128: a switch
+                            back costs a pass over the frontier bitmap,
+                            and a late bottom-up step is cheap) */
   int32_t block;         /* threads per workgroup: 256, 512 or 1024 */
   int32_t blocks_per_cu; /* persistent grid: workgroups per compute unit
                             (0 = as many as fit) */

@@ -5,21 +5,25 @@ all input graphs.  This tuner therefore searches only hardware-facing
 parameters (direction-switch thresholds, workgroup size and persistent
 workgroups per CU, hub splitting, the bottom-up mapping, the level schedule,
 the batched thresholds and tile shape) on a fixed tuning set of graphs of
-the benchmark's shapes at reduced size (R-MAT, uniform-random and road-like
-grid searches; R-MAT, uniform-random and mixed multi-source batches), and
+the benchmark's shapes with other seeds (R-MAT and uniform-random searches at
+the benchmark's scale, a smaller road-like grid; R-MAT, uniform-random and
+mixed multi-source batches at reduced size), and
 writes the winner to ``tuned/<arch>_<CUs>cu.json``.  The binding applies that file when it loads
 the library on a device of that model.  Parameters never change results:
 depths are unique and every schedule returns valid parents.
 
 Search: coordinate descent from the library defaults; each coordinate takes
-the value of least score, where the score is the geometric mean over the
-tuning items of (time with the candidate set) / (time with the defaults).
+the value of least score, where the score is the geometric mean of (time
+with the candidate set) / (time with the defaults) over the tuning items
+that the coordinate acts on (single searches for the single-source knobs,
+batches for the batched ones).
 
     python -m paper_1508_03619_amd.autotune [--passes 2] [--dry-run]
 """
 from __future__ import annotations
 
 import argparse
+import inspect
 import json
 import math
 import os
@@ -33,7 +37,7 @@ TUNED_DIR = os.path.join(_HERE, "tuned")
 # Candidate values per parameter (all legal for gap_set_params).
 SPACE: Dict[str, List[int]] = {
     "alpha": [4, 8, 12, 15, 20, 30, 50],
-    "beta": [6, 12, 18, 24, 48, 96],
+    "beta": [6, 12, 18, 24, 48, 96, 128, 256, 512],
     "block": [256, 512, 1024],
     "hub_degree": [64, 128, 256, 512, 1024],
     "chunk_edges": [128, 256, 512, 1024],
@@ -52,10 +56,23 @@ ORDER = ["block", "blocks_per_cu", "alpha", "beta", "hub_degree", "chunk_edges",
          "lds_bitmap", "bu_mapping", "td_plain", "batch_alpha", "batch_beta", "batch_words", "mode",
          "graph_chunk"]
 
-# Tuning set: the benchmark's graph shapes at reduced size, other seeds.
+# The items each parameter acts on (kinds of TUNING_SET entries): a knob of
+# the single-source search (the persistent grid's shape included) is judged
+# on single searches only, so a gain there is not diluted by batches it does
+# not touch.  Unlisted: every item.
+AFFECTS: Dict[str, tuple] = {
+    **{k: ("single",) for k in ("block", "blocks_per_cu", "alpha", "beta", "hub_degree", "chunk_edges",
+                                "small_frontier", "lds_bitmap", "bu_mapping", "td_plain", "mode",
+                                "graph_chunk")},
+    **{k: ("batch",) for k in ("batch_alpha", "batch_beta", "batch_words")},
+}
+
+# Tuning set: the benchmark's graph shapes with other seeds; single searches
+# at the benchmark's scale (the workgroup shape that wins at scale 21 loses
+# at scale 22), the grid and the batches smaller.
 TUNING_SET = [
-    {"kind": "single", "graph": ("rmat", 21, 7001), "sources": 8},
-    {"kind": "single", "graph": ("urand", 21, 7002), "sources": 8},
+    {"kind": "single", "graph": ("rmat", 22, 7001), "sources": 32},
+    {"kind": "single", "graph": ("urand", 22, 7002), "sources": 32},
     {"kind": "single", "graph": ("grid", 1024, 7003), "sources": 4},
     {"kind": "batch", "graphs": [("rmat", 21, 7001)], "lanes": 64},
     {"kind": "batch", "graphs": [("urand", 21, 7002)], "lanes": 64},
@@ -83,36 +100,41 @@ def read_tuned(path: str) -> dict:
 
 
 def coordinate_descent(space: Dict[str, Sequence[int]], order: Sequence[str], start: Dict[str, int],
-                       score: Callable[[Dict[str, int]], float], passes: int = 2,
+                       score: Callable[..., float], passes: int = 2,
                        min_gain: float = 0.01, log=print) -> tuple:
     """Minimise ``score`` one coordinate at a time.  A new value must beat the
-    incumbent by ``min_gain`` (relative) to be taken.  Returns (best params,
-    best score, number of evaluations)."""
+    incumbent by ``min_gain`` (relative) to be taken.  ``score(p)`` scores a
+    parameter set; a score that takes two arguments, ``score(p, name)``, is
+    asked while coordinate ``name`` moves (a candidate and the incumbent are
+    compared on the same measure) and with name None for the final score.
+    Returns (best params, best score, number of distinct parameter sets
+    scored)."""
+    two = len(inspect.signature(score).parameters) >= 2
     cache: Dict[tuple, float] = {}
 
-    def ev(p):
-        key = tuple(sorted(p.items()))
+    def ev(p, name=None):
+        key = (tuple(sorted(p.items())), name if two else None)
         if key not in cache:
-            cache[key] = score(p)
+            cache[key] = score(p, name) if two else score(p)
         return cache[key]
 
     best = dict(start)
-    best_s = ev(best)
     for ps in range(passes):
         changed = False
         for name in order:
+            inc = ev(best, name)
             for v in space[name]:
                 if v == best[name]:
                     continue
                 cand = dict(best)
                 cand[name] = v
-                s = ev(cand)
-                if s < best_s * (1.0 - min_gain):
-                    log(f"  pass {ps}: {name}={v} score {s:.4f} (was {best_s:.4f})")
-                    best, best_s, changed = cand, s, True
+                s = ev(cand, name)
+                if s < inc * (1.0 - min_gain):
+                    log(f"  pass {ps}: {name}={v} score {s:.4f} (was {inc:.4f})")
+                    best, inc, changed = cand, s, True
         if not changed:
             break
-    return best, best_s, len(cache)
+    return best, ev(best), len({k[0] for k in cache})
 
 
 # ---------------------------------------------------------------------------
@@ -202,11 +224,19 @@ def main(argv=None):
     base = bench.measure(defaults)
     log("defaults: " + ", ".join(f"{b:.3f}" for b in base) + " ms")
 
-    def score(p):
-        full = dict(defaults)
-        full.update(p)
-        t = bench.measure(full)
-        return math.exp(sum(math.log(x / y) for x, y in zip(t, base)) / len(t))
+    measured: Dict[tuple, List[float]] = {}
+
+    def score(p, name):
+        # geometric mean of the time ratios over the items `name` acts on
+        # (every item for name None)
+        key = tuple(sorted(p.items()))
+        if key not in measured:
+            full = dict(defaults)
+            full.update(p)
+            measured[key] = bench.measure(full)
+        kinds = AFFECTS.get(name, ("single", "batch"))
+        pairs = [(x, y) for x, y, it in zip(measured[key], base, TUNING_SET) if it["kind"] in kinds]
+        return math.exp(sum(math.log(x / y) for x, y in pairs) / len(pairs))
 
     # a candidate must beat the incumbent by 2 %: run-to-run noise of the
     # timings is about 1 %

@@ -193,7 +193,7 @@ static gap_params default_params() {
   p.mode = GAP_MODE_PERSISTENT;
   p.direction = GAP_DIR_AUTO;
   p.alpha = 15;
-  p.beta = 18;
+  p.beta = 128;
   p.block = 1024;
   p.blocks_per_cu = 1;
   p.hub_degree = 256;

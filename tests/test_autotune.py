@@ -2,6 +2,7 @@
 the validity of any committed tuned parameter file."""
 import glob
 import json
+import math
 import os
 
 import pytest
@@ -29,6 +30,37 @@ def test_coordinate_descent_ignores_noise_below_min_gain():
     best, _, _ = at.coordinate_descent(space, ["a"], {"a": 2}, lambda p: 1.0 - 0.001 * p["a"],
                                        passes=2, min_gain=0.01, log=lambda m: None)
     assert best == {"a": 2}
+
+
+def test_coordinate_descent_scores_each_coordinate_on_its_own_items():
+    """A two-argument score is asked per coordinate: a gain on the items a
+    coordinate acts on counts in full, not diluted by items it leaves alone."""
+    space = {"a": [1, 2], "b": [1, 2]}
+    # a halves item 0's time only; b changes nothing
+    def times(p):
+        return [1.0 if p["a"] == 1 else 0.97, 1.0, 1.0, 1.0]
+    acts = {"a": [0], "b": [0, 1, 2, 3], None: [0, 1, 2, 3]}
+
+    def score(p, name):
+        t = times(p)
+        idx = acts[name]
+        return math.exp(sum(math.log(t[i]) for i in idx) / len(idx))
+
+    best, s, nev = at.coordinate_descent(space, ["a", "b"], {"a": 1, "b": 1}, score, passes=2,
+                                         min_gain=0.02, log=lambda m: None)
+    assert best == {"a": 2, "b": 1}  # 3 % on its own item; 0.76 % over all four
+    assert s == pytest.approx(0.97 ** 0.25)
+    assert nev == 3
+    # the same gain scored over every item stays below min_gain
+    best1, _, _ = at.coordinate_descent(space, ["a", "b"], {"a": 1, "b": 1},
+                                        lambda p: score(p, None), passes=2, min_gain=0.02,
+                                        log=lambda m: None)
+    assert best1 == {"a": 1, "b": 1}
+
+
+def test_affects_names_tuned_parameters():
+    assert set(at.AFFECTS) <= set(at.SPACE)
+    assert all(set(k) <= {"single", "batch"} for k in at.AFFECTS.values())
 
 
 def test_space_covers_order_and_names_are_library_parameters():
