@@ -267,8 +267,8 @@ __device__ __forceinline__ void bfs_persistent(const SearchArgs &a) {
       const unsigned long long scanned = t.scanned;  // thread 0's
       if (!grid_sync(a.ctl, nblocks, Totals{}, -1, 0, a.p.wait)) return;
       step_begin<BLOCK>(s, st, false);
-      convert_to_bitmaps(a.g, a.parent, a.depth, d + 1, (fsel ? a.bm1 : a.bm0), a.vbm, gwave, nwaves,
-                         &acc);
+      convert_to_bitmaps<true>(a.g, a.parent, a.depth, d + 1, (fsel ? a.bm1 : a.bm0), a.vbm, gwave,
+                               nwaves, &acc);
       t = step_end<BLOCK>(s, st, acc);
       t.scanned += scanned;
     }

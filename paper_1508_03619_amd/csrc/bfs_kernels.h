@@ -334,7 +334,7 @@ __device__ inline Totals step_end(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &
 // batches at once: the parent probes, then the CAS claims, are issued
 // back-to-back so their latencies overlap; then the winners are appended.
 template <int BLOCK, bool STATS, int NK = 4>
-__device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
+__device__ __forceinline__ void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
                                  const int32_t (&v)[4], const int32_t (&u)[4]) {
   // loads without branches: a load under a per-lane condition gets a block
   // of its own that waits for it before the next load issues
@@ -368,7 +368,7 @@ __device__ inline void td_claim4(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &a
 // appended: F_{d+1} is read back from the depths after the level's barrier
 // (convert_to_bitmaps with totals), which also counts it exactly once.
 template <bool STATS, int NK = 4>
-__device__ inline void td_plain4(const StepArgs &a, LaneAcc &acc, const int32_t (&v)[4],
+__device__ __forceinline__ void td_plain4(const StepArgs &a, LaneAcc &acc, const int32_t (&v)[4],
                                  const int32_t (&u)[4]) {
   int32_t p[4];
 #pragma unroll
@@ -388,7 +388,7 @@ __device__ inline void td_plain4(const StepArgs &a, LaneAcc &acc, const int32_t 
 // case on small frontiers) probes and claims one batch, not four of which
 // three are empty.
 template <int BLOCK, bool STATS, bool PLAIN>
-__device__ inline void td_claims(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
+__device__ __forceinline__ void td_claims(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc,
                                  const int32_t (&v)[4], const int32_t (&u)[4], int64_t left) {
   if (left <= kWave) {
     if constexpr (PLAIN)
@@ -415,7 +415,7 @@ __device__ inline void td_claims(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &a
 // waves, which measured faster there (17.6 against 20.7 us per level on a
 // 4096^2 grid).  PLAIN: claims by plain stores (td_plain4), no appends.
 template <int BLOCK, bool STATS, bool SPREAD = false, bool PLAIN = false>
-__device__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
+__device__ __forceinline__ void td_step(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t gwave,
                         int64_t nwaves) {
   const int lane = lane_id();
   const int2 *cin = a.Q.cs(a.bs_in);
@@ -732,7 +732,7 @@ __host__ __device__ constexpr int64_t bu_refill_words() {
 }
 
 template <int BLOCK, bool STATS, int J>
-__device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t wlo,
+__device__ __forceinline__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc, int64_t wlo,
                                int64_t whi, uint64_t *lfbm, int64_t lw) {
   uint64_t *found = reinterpret_cast<uint64_t *>(st.q);
   unsigned int *cursor = &st.hbase;
@@ -920,7 +920,7 @@ __device__ void bu_step_refill(const StepArgs &a, Stage<BLOCK> &st, LaneAcc &acc
 // workgroups; the staged entries reach the segments in step_end, and a
 // barrier that publishes bs_out must follow.
 template <int BLOCK>
-__device__ void queue_from_bitmap(const StepArgs &a, Stage<BLOCK> &st, const uint64_t *fbm,
+__device__ __forceinline__ void queue_from_bitmap(const StepArgs &a, Stage<BLOCK> &st, const uint64_t *fbm,
                                   int64_t gwave, int64_t nwaves) {
   if (threadIdx.x == 0) {
     st.qn = 0;
@@ -961,9 +961,10 @@ __device__ void queue_from_bitmap(const StepArgs &a, Stage<BLOCK> &st, const uin
 // visited bitmap (parent >= 0; vertices that no edge enters and padding
 // count as visited so whole words can be skipped).  Undirected, "no edge
 // enters" is degree 0, which the parent encoding already holds; directed,
-// it is in-degree 0, read from the in-lists.  acc: also count F_d into it
-// (vertices, and their out-degrees read from the row offsets) -- after a
-// level of plain-store claims, the frontier's only exact count.
+// it is in-degree 0, read from the in-lists.  COUNT: also count F_d into
+// acc (vertices, and their out-degrees read from the row offsets) -- after
+// a level of plain-store claims, the frontier's only exact count.
+template <bool COUNT = false>
 __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *parent,
                                           const int32_t *depth, int32_t d, uint64_t *fbm,
                                           uint64_t *vbm, int64_t gwave, int64_t nwaves,
@@ -971,17 +972,24 @@ __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *pare
   const int lane = lane_id();
   const int64_t nwords = (g.n + kWave - 1) / kWave;
   // kConvU words per pass: all their loads are issued before the first
-  // ballot waits, so a wave keeps 2 * kConvU loads in flight
+  // ballot waits, so a wave keeps 2 * kConvU loads in flight (4 * kConvU
+  // when COUNT: the row offsets that give a frontier vertex's degree are
+  // loaded for every lane, not behind a per-lane test)
   constexpr int kConvU = 4;
   const int32_t spare = (int32_t)(((uint64_t)gwave * 1024ull) % (uint64_t)g.n);
   for (int64_t w0 = gwave; w0 < nwords; w0 += kConvU * nwaves) {
     int32_t p[kConvU], dv[kConvU];
+    int64_t r0[kConvU], r1[kConvU];
 #pragma unroll
     for (int u = 0; u < kConvU; ++u) {
       const int64_t v = (w0 + u * nwaves) * kWave + lane;
       const bool in = w0 + u * nwaves < nwords && v < g.n;
       const int64_t vl = in ? v : (int64_t)spare;
       const int32_t pr = parent[vl], dr = depth[vl];
+      if (COUNT) {
+        r0[u] = g.row_ptr[vl];
+        r1[u] = g.row_ptr[vl + 1];
+      }
       p[u] = in ? pr : 0;
       dv[u] = in ? dr : -1;
     }
@@ -1004,9 +1012,9 @@ __device__ inline void convert_to_bitmaps(const DevGraph &g, const int32_t *pare
         vbm[w] = bv;
         fbm[w] = bf;
       }
-      if (acc && front) {
+      if (COUNT && front) {
         acc->nv += 1;
-        acc->mf += (unsigned long long)(g.row_ptr[v + 1] - g.row_ptr[v]);
+        acc->mf += (unsigned long long)(r1[u] - r0[u]);
       }
     }
   }
