@@ -5,9 +5,9 @@ all input graphs.  This tuner therefore searches only hardware-facing
 parameters (direction-switch thresholds, workgroup size and persistent
 workgroups per CU, hub splitting, the bottom-up mapping, the level schedule,
 the batched thresholds and tile shape) on a fixed tuning set of graphs of
-the benchmark's shapes with other seeds (R-MAT and uniform-random searches at
-the benchmark's scale, a smaller road-like grid; R-MAT, uniform-random and
-mixed multi-source batches at reduced size), and
+the benchmark's shapes with other seeds (R-MAT and uniform-random searches and
+batches at the benchmark's scale, a smaller road-like grid, smaller mixed
+and 256-lane batches), and
 writes the winner to ``tuned/<arch>_<CUs>cu.json``.  The binding applies that file when it loads
 the library on a device of that model.  Parameters never change results:
 depths are unique and every schedule returns valid parents.
@@ -67,15 +67,16 @@ AFFECTS: Dict[str, tuple] = {
     **{k: ("batch",) for k in ("batch_alpha", "batch_beta", "batch_words")},
 }
 
-# Tuning set: the benchmark's graph shapes with other seeds; single searches
-# at the benchmark's scale (the workgroup shape that wins at scale 21 loses
-# at scale 22), the grid and the batches smaller.
+# Tuning set: the benchmark's graph shapes with other seeds; R-MAT and
+# uniform searches and 64-lane batches at the benchmark's scale (the
+# workgroup shape and the batched switch threshold that win at scale 21 lose
+# at scale 22), the grid and the mixed and 256-lane batches smaller.
 TUNING_SET = [
     {"kind": "single", "graph": ("rmat", 22, 7001), "sources": 32},
     {"kind": "single", "graph": ("urand", 22, 7002), "sources": 32},
     {"kind": "single", "graph": ("grid", 1024, 7003), "sources": 4},
-    {"kind": "batch", "graphs": [("rmat", 21, 7001)], "lanes": 64},
-    {"kind": "batch", "graphs": [("urand", 21, 7002)], "lanes": 64},
+    {"kind": "batch", "graphs": [("rmat", 22, 7001)], "lanes": 64},
+    {"kind": "batch", "graphs": [("urand", 22, 7002)], "lanes": 64},
     {"kind": "batch", "graphs": [("rmat", s, 7100 + s) for s in (14, 15, 16, 17, 18)], "lanes": 16},
     {"kind": "batch", "graphs": [("rmat", 20, 7020)], "lanes": 256},
 ]
