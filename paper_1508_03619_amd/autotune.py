@@ -59,11 +59,10 @@ ORDER = ["block", "blocks_per_cu", "alpha", "beta", "hub_degree", "chunk_edges",
 # The items each parameter acts on (kinds of TUNING_SET entries): a knob of
 # the single-source search (the persistent grid's shape included) is judged
 # on single searches only, so a gain there is not diluted by batches it does
-# not touch.  Unlisted: every item.
+# not touch.  Unlisted (hub splitting, which both kernels use): every item.
 AFFECTS: Dict[str, tuple] = {
-    **{k: ("single",) for k in ("block", "blocks_per_cu", "alpha", "beta", "hub_degree", "chunk_edges",
-                                "small_frontier", "lds_bitmap", "bu_mapping", "td_plain", "mode",
-                                "graph_chunk")},
+    **{k: ("single",) for k in ("block", "blocks_per_cu", "alpha", "beta", "small_frontier",
+                                "lds_bitmap", "bu_mapping", "td_plain", "mode", "graph_chunk")},
     **{k: ("batch",) for k in ("batch_alpha", "batch_beta", "batch_words")},
 }
 

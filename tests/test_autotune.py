@@ -61,6 +61,9 @@ def test_coordinate_descent_scores_each_coordinate_on_its_own_items():
 def test_affects_names_tuned_parameters():
     assert set(at.AFFECTS) <= set(at.SPACE)
     assert all(set(k) <= {"single", "batch"} for k in at.AFFECTS.values())
+    # hub splitting is used by single searches and batches alike
+    assert "hub_degree" not in at.AFFECTS and "chunk_edges" not in at.AFFECTS
+    assert at.AFFECTS["batch_alpha"] == ("batch",) and at.AFFECTS["block"] == ("single",)
 
 
 def test_space_covers_order_and_names_are_library_parameters():
